@@ -1,0 +1,178 @@
+/*
+ * sr.h -- C ABI of the MI355X (gfx950) synchronous-relaxation library for the
+ * continuous-time n-fold way Ising simulation (Lubachevsky & Weiss,
+ * "Synchronous relaxation for parallel Ising spin simulations").
+ *
+ * Problem statement (Sec. 2): a rectangular Lx x Ly lattice with periodic
+ * boundaries, spins +-1, four nearest neighbours, energy of eq. hamil
+ * E = -J sum_<nn bonds> s s' - h sum s (every bond counted once), flip
+ * probability p of eq. pMin (Metropolis) or eq. pglauber (Glauber) at
+ * temperature T (k_B = 1); every site attempts flips as a Poisson process of
+ * rate lambda = 1 (Sec. 3), so time is measured in units of 1/lambda.
+ * Method (Secs. 4-5): the lattice is cut into bx x by subdomains (the
+ * paper's PEs; one GPU wavefront each); each subdomain runs the rejection-free
+ * n-fold way over a window [t_c, t_c + window) reading its neighbours'
+ * boundary flip histories of the previous iteration (none in the first
+ * iteration: the canonical assumption); iterations repeat until no boundary
+ * history changes, then committed time t_c advances by the window (Sec. 4
+ * box).  Random numbers are a presimulated list (Philox-4x32-10 keyed by the
+ * seed, counter = (event index, subdomain)), reused across iterations and
+ * carried across windows (Sec. 5, "Subsequent steps"), so the converged
+ * trajectory does not depend on the window length.
+ *
+ * Integer conventions fixed by the library: ticks of 2^-tick_bits time units
+ * (int64); rates as round(2^28 p); -log U as a Q(28 + tick_bits) fixed-point
+ * integer; an event falls on the first tick at which the integrated hazard
+ * reaches -log U (eq. lambdataua on the tick grid); simultaneous events of
+ * different subdomains all choose from the state before their tick.
+ *
+ * Ownership: the library owns every device buffer of a simulation; callers
+ * own every host buffer they pass.  All device work of a simulation is
+ * ordered on the HIP stream given at creation (NULL = default stream); every
+ * call returns only after that work is complete.  Handles are not
+ * thread-safe: one host thread per handle at a time.
+ *
+ * Errors: functions return SR_OK (0) or a negative SR_E* code; the message of
+ * the last failure of a handle is sr_last_error(handle) (creation failures:
+ * sr_last_error(NULL)).
+ */
+#ifndef SR_H
+#define SR_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SR_OK = 0,
+  SR_EINVAL = -1,    /* invalid argument or parameter combination */
+  SR_ENOMEM = -2,    /* device or host allocation failed */
+  SR_EOVERFLOW = -3, /* a history buffer could not be grown any further */
+  SR_ENOCONV = -4,   /* max_iters reached; the window was NOT committed */
+  SR_EDEVICE = -5,   /* a HIP call or kernel failed */
+  SR_EDONE = -6      /* committed time already equals the horizon */
+};
+
+enum { SR_METROPOLIS = 0, SR_GLAUBER = 1 };                 /* eq. pMin / eq. pglauber */
+enum { SR_INIT_RANDOM = 0, SR_INIT_ALL_UP = 1, SR_INIT_USER = 2 };
+enum { SR_LOG_DIGEST = 0, SR_LOG_FULL = 1 };
+
+typedef struct {
+  int32_t Lx, Ly;            /* lattice (Sec. 2); 4 <= Lx, Ly; periodic */
+  int32_t bx, by;            /* subdomain block (Sec. 5 partition G -> G_i):
+                                Lx % bx == 0, Ly % by == 0, 2 <= bx, by <= 64,
+                                bx*by <= 1024, and bx is a multiple of
+                                max(1, bx*by/64) rounded up to a power of 2.
+                                bx = by = 0: chosen by the tuner */
+  double J, h, T;            /* coupling J > 0 allowed any sign, field, T > 0 */
+  int32_t rule;              /* SR_METROPOLIS or SR_GLAUBER */
+  double window;             /* T_max of Sec. 4/5 in time units (> 0);
+                                0 = chosen by the tuner */
+  double horizon;            /* simulate [0, horizon) (>= 0) */
+  uint64_t seed;             /* Philox key */
+  int32_t init;              /* SR_INIT_* */
+  const int8_t* init_spins;  /* host, Ly*Lx row-major (+1/-1), read during
+                                sr_create only; SR_INIT_USER only */
+  int32_t log_mode;          /* SR_LOG_DIGEST or SR_LOG_FULL (every committed
+                                (tick, site) kept on the host) */
+  int32_t max_iters;         /* iterations per window before SR_ENOCONV
+                                (0 = 10000) */
+  int32_t tick_bits;         /* 0 = 28; 4..28 */
+  int32_t hist_cap;          /* initial entries per boundary list and window
+                                (0 = sized from the window; grown and the
+                                window re-run on overflow) */
+  int32_t wlog_cap;          /* initial events per subdomain and window
+                                (0 = sized from the window; grown likewise) */
+} sr_params;
+
+typedef struct {
+  int64_t tick;              /* committed time in ticks */
+  int64_t M;                 /* sum of spins at committed time */
+  int64_t bond_sum;          /* sum over right and down bonds of s s' */
+  int64_t flips;             /* committed flips so far */
+  int64_t events_processed;  /* flips simulated in all iterations so far */
+  int64_t windows;           /* committed windows so far */
+  int64_t iterations;        /* relaxation iterations so far */
+  int32_t last_g;            /* iterations of the last committed window */
+  int32_t last_f;            /* max boundary-site events of one subdomain in
+                                one iteration of the last window (Sec. 6 f) */
+  int32_t tick_bits;
+  int32_t n_sub;             /* number of subdomains */
+  int32_t bx, by;            /* block in use */
+  int32_t Lx, Ly;            /* lattice */
+  int64_t window_ticks;      /* window in use */
+  int64_t horizon_ticks;
+} sr_obs;
+
+typedef struct sr_sim sr_sim;
+
+/* Create a simulation: validates the parameters, builds the rate table
+ * (eqs. pMin / pglauber on the host in IEEE double), allocates the device
+ * state and sets the initial spins (Sec. 4: "set to initial states").
+ * `hip_stream` is a hipStream_t (or NULL).  On success *out owns the handle. */
+int sr_create(const sr_params* p, void* hip_stream, sr_sim** out);
+
+/* Advance committed time by up to n_windows windows (Sec. 4 box: iterate
+ * generate / synchronise / compare / synchronise until no history changes,
+ * then increment committed time); n_windows < 0 runs to the horizon.  The last
+ * window is truncated at the horizon.  iters_out (may be NULL) receives g of
+ * each committed window.  *n_done (may be NULL) = windows committed.  On
+ * SR_ENOCONV the failing window is left uncommitted and earlier ones stay. */
+int sr_run_window(sr_sim* s, int32_t n_windows, int32_t* iters_out, int32_t* n_done);
+
+/* Observables at committed time (eq. hamil parts): M, bond sum, counters. */
+int sr_observables(sr_sim* s, sr_obs* out);
+
+/* Release everything.  NULL-safe. */
+void sr_destroy(sr_sim* s);
+
+/* Committed spins, Ly*Lx int8 row-major, into a caller-owned host buffer. */
+int sr_get_spins(sr_sim* s, int8_t* host_out);
+
+/* SR_LOG_FULL only: committed events of subdomain d (row-major block id) in
+ * time order: ticks[i], global sites[i] (y*Lx + x).  Copies min(n, cap)
+ * entries; *n = total. */
+int sr_get_log(sr_sim* s, int32_t d, int64_t* ticks, int64_t* sites, int64_t cap, int64_t* n);
+
+/* Per-subdomain event digests (order-free 64-bit sum over committed events
+ * of mix(mix(tick) + global site), mix = SplitMix64 finaliser) and committed
+ * flip counts; caller-owned arrays of n_sub entries (either may be NULL). */
+int sr_get_digests(sr_sim* s, uint64_t* digests, int64_t* flips);
+
+/* Per-subdomain carry at committed time: (j, anchor, acc) = index of the
+ * pending random pair, tick of the last event or break point, integrated
+ * hazard since then.  Caller-owned, 3 * n_sub int64. */
+int sr_get_carry(sr_sim* s, int64_t* out);
+
+/* The 10 class rates round(2^28 p_k), class k = 5*[s = -1] + (up neighbours). */
+int sr_get_rate_table(sr_sim* s, uint32_t out[10]);
+
+/* Checkpoint of the committed state (committed time is a consistent cut,
+ * Sec. 4).  sr_save with host_blob = NULL reports the size in *n. */
+int sr_save(sr_sim* s, void* host_blob, size_t cap, size_t* n);
+int sr_load(const void* host_blob, size_t n, void* hip_stream, sr_sim** out);
+
+/* Message of the last failure (NULL handle: last creation/load failure). */
+const char* sr_last_error(const sr_sim* s);
+
+/* ---- batched form: many independent lattices in one persistent launch ----
+ * Runs every listed simulation to its horizon with one persistent kernel:
+ * resident wavefronts pop (lattice, subdomain) tasks from a device work queue;
+ * the last task of a lattice's iteration decides convergence and enqueues the
+ * next iteration or the next window.  Results are bit-identical to
+ * sr_run_window on each simulation alone.  All simulations must use
+ * SR_LOG_DIGEST and the same stream. */
+int sr_batch_run(sr_sim* const* sims, int32_t n, void* hip_stream);
+
+/* ---- tuner ---- choose block and window for a lattice (used when bx = by
+ * = 0 or window = 0): block from a fixed table over (L, T, h); window from the
+ * step-size rule T_max ~ log N / |dG| of Sec. 5 scaled by a factor learned from
+ * measured iterations per window.  Deterministic for given inputs. */
+int sr_tune(const sr_params* p, int32_t* bx, int32_t* by, double* window);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SR_H */

@@ -1,0 +1,258 @@
+"""Python binding of the MI355X synchronous-relaxation library (libsr.so).
+
+Argument marshalling only: every step of the simulation runs in the HIP
+kernels behind the C ABI declared in ``include/sr.h``.  The library must have
+been built (``python -m paper_cs_0405053_amd.build`` or
+``__graft_entry__.build()``); importing this module without it raises.
+
+Typical use::
+
+    import paper_cs_0405053_amd as sr
+    sim = sr.Sim(dict(Lx=64, Ly=64, bx=16, by=16, J=1.0, h=0.0, T=1.5,
+                      window=1.0, horizon=50.0, seed=1))
+    g = sim.run()                 # iterations per committed window
+    obs = sim.observables()
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsr.so")
+
+SR_OK, SR_EINVAL, SR_ENOMEM, SR_EOVERFLOW, SR_ENOCONV, SR_EDEVICE, SR_EDONE = 0, -1, -2, -3, -4, -5, -6
+_RULE = {"metropolis": 0, "glauber": 1, 0: 0, 1: 1}
+_INIT = {"random": 0, "up": 1, "user": 2, 0: 0, 1: 1, 2: 2}
+_LOG = {"digest": 0, "full": 1, 0: 0, 1: 1}
+
+# every function the C ABI exports (include/sr.h)
+EXPORTS = ["sr_create", "sr_run_window", "sr_observables", "sr_destroy", "sr_get_spins",
+           "sr_get_log", "sr_get_digests", "sr_get_carry", "sr_get_rate_table", "sr_save",
+           "sr_load", "sr_last_error", "sr_batch_run", "sr_tune"]
+
+
+class SRError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("Lx", C.c_int32), ("Ly", C.c_int32), ("bx", C.c_int32), ("by", C.c_int32),
+                ("J", C.c_double), ("h", C.c_double), ("T", C.c_double), ("rule", C.c_int32),
+                ("window", C.c_double), ("horizon", C.c_double), ("seed", C.c_uint64),
+                ("init", C.c_int32), ("init_spins", C.c_void_p), ("log_mode", C.c_int32),
+                ("max_iters", C.c_int32), ("tick_bits", C.c_int32), ("hist_cap", C.c_int32),
+                ("wlog_cap", C.c_int32)]
+
+
+class Obs(C.Structure):
+    _fields_ = [("tick", C.c_int64), ("M", C.c_int64), ("bond_sum", C.c_int64),
+                ("flips", C.c_int64), ("events_processed", C.c_int64), ("windows", C.c_int64),
+                ("iterations", C.c_int64), ("last_g", C.c_int32), ("last_f", C.c_int32),
+                ("tick_bits", C.c_int32), ("n_sub", C.c_int32), ("bx", C.c_int32),
+                ("by", C.c_int32), ("Lx", C.c_int32), ("Ly", C.c_int32),
+                ("window_ticks", C.c_int64), ("horizon_ticks", C.c_int64)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libsr.so; raises if it was never built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_cs_0405053_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.sr_create.argtypes = [C.POINTER(Params), P, C.POINTER(P)]
+        L.sr_run_window.argtypes = [P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.sr_observables.argtypes = [P, C.POINTER(Obs)]
+        L.sr_destroy.argtypes = [P]
+        L.sr_destroy.restype = None
+        L.sr_get_spins.argtypes = [P, P]
+        L.sr_get_log.argtypes = [P, C.c_int32, P, P, C.c_int64, C.POINTER(C.c_int64)]
+        L.sr_get_digests.argtypes = [P, P, P]
+        L.sr_get_carry.argtypes = [P, P]
+        L.sr_get_rate_table.argtypes = [P, P]
+        L.sr_save.argtypes = [P, P, C.c_size_t, C.POINTER(C.c_size_t)]
+        L.sr_load.argtypes = [P, C.c_size_t, P, C.POINTER(P)]
+        L.sr_last_error.argtypes = [P]
+        L.sr_last_error.restype = C.c_char_p
+        L.sr_batch_run.argtypes = [P, C.c_int32, P]
+        L.sr_tune.argtypes = [C.POINTER(Params), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                              C.POINTER(C.c_double)]
+        _lib = L
+    return _lib
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)           # a torch.cuda.Stream
+
+
+def to_params(p: Dict) -> (Params, Optional[np.ndarray]):
+    cp = Params()
+    cp.Lx, cp.Ly = int(p["Lx"]), int(p["Ly"])
+    cp.bx, cp.by = int(p.get("bx", 0)), int(p.get("by", 0))
+    cp.J, cp.h, cp.T = float(p.get("J", 1.0)), float(p.get("h", 0.0)), float(p["T"])
+    cp.rule = _RULE[p.get("rule", "metropolis")]
+    cp.window, cp.horizon = float(p.get("window", 0.0)), float(p["horizon"])
+    cp.seed = int(p.get("seed", 0)) & (2**64 - 1)
+    cp.init = _INIT[p.get("init", "random")]
+    keep = None
+    if cp.init == 2 and p.get("init_spins") is not None:
+        keep = np.ascontiguousarray(p["init_spins"], dtype=np.int8).reshape(-1)
+        if keep.size != cp.Lx * cp.Ly:
+            raise SRError(SR_EINVAL, "init_spins must hold Lx*Ly values")
+        cp.init_spins = keep.ctypes.data
+    cp.log_mode = _LOG[p.get("log_mode", "digest")]
+    cp.max_iters = int(p.get("max_iters", 0))
+    cp.tick_bits = int(p.get("tick_bits", 0))
+    cp.hist_cap = int(p.get("hist_cap", 0))
+    cp.wlog_cap = int(p.get("wlog_cap", 0))
+    return cp, keep
+
+
+def last_error(handle=None) -> str:
+    m = lib().sr_last_error(handle)
+    return m.decode() if m else ""
+
+
+def tune(p: Dict):
+    """(bx, by, window) the tuner would choose."""
+    cp, _ = to_params(p)
+    bx, by, w = C.c_int32(), C.c_int32(), C.c_double()
+    rc = lib().sr_tune(C.byref(cp), C.byref(bx), C.byref(by), C.byref(w))
+    if rc != SR_OK:
+        raise SRError(rc, "tuner rejected the lattice")
+    return bx.value, by.value, w.value
+
+
+class Sim:
+    """One lattice simulation (owns its device state)."""
+
+    def __init__(self, p: Dict = None, stream=None, _handle=None):
+        self._h = None
+        if _handle is not None:
+            self._h = _handle
+            return
+        cp, keep = to_params(p)
+        h = C.c_void_p()
+        rc = lib().sr_create(C.byref(cp), _stream_ptr(stream), C.byref(h))
+        del keep
+        if rc != SR_OK:
+            raise SRError(rc, last_error(None))
+        self._h = h
+
+    # -- lifetime
+    def close(self):
+        if self._h is not None:
+            lib().sr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, rc, what):
+        if rc != SR_OK:
+            raise SRError(rc, f"{what}: {last_error(self._h)}")
+
+    @property
+    def handle(self):
+        return self._h
+
+    # -- the method
+    def run(self, n_windows: int = -1) -> np.ndarray:
+        """Commit up to n_windows windows (all remaining if < 0); returns the
+        iterations g of each committed window."""
+        o = self.observables()
+        left = -(-(o["horizon_ticks"] - o["tick"]) // o["window_ticks"])
+        n = left if n_windows < 0 else min(n_windows, left)
+        g = np.zeros(max(n, 1), dtype=np.int32)
+        done = C.c_int32()
+        rc = lib().sr_run_window(self._h, n_windows, g.ctypes.data_as(C.POINTER(C.c_int32)),
+                                 C.byref(done))
+        self._check(rc, "sr_run_window")
+        return g[:done.value].copy()
+
+    def observables(self) -> Dict:
+        o = Obs()
+        self._check(lib().sr_observables(self._h, C.byref(o)), "sr_observables")
+        return {k: getattr(o, k) for k, _ in Obs._fields_}
+
+    def spins(self) -> np.ndarray:
+        o = self.observables()
+        buf = np.zeros(o["Ly"] * o["Lx"], dtype=np.int8)
+        self._check(lib().sr_get_spins(self._h, buf.ctypes.data), "sr_get_spins")
+        return buf.reshape(o["Ly"], o["Lx"])
+
+    def log(self, d: int):
+        n = C.c_int64()
+        self._check(lib().sr_get_log(self._h, d, None, None, 0, C.byref(n)), "sr_get_log")
+        t = np.zeros(max(n.value, 1), dtype=np.int64)
+        v = np.zeros(max(n.value, 1), dtype=np.int64)
+        self._check(lib().sr_get_log(self._h, d, t.ctypes.data, v.ctypes.data, n.value,
+                                     C.byref(n)), "sr_get_log")
+        return t[:n.value], v[:n.value]
+
+    def digests(self):
+        n = self.observables()["n_sub"]
+        dg = np.zeros(n, dtype=np.uint64)
+        fl = np.zeros(n, dtype=np.int64)
+        self._check(lib().sr_get_digests(self._h, dg.ctypes.data, fl.ctypes.data),
+                    "sr_get_digests")
+        return dg, fl
+
+    def carry(self) -> np.ndarray:
+        n = self.observables()["n_sub"]
+        c = np.zeros(3 * n, dtype=np.int64)
+        self._check(lib().sr_get_carry(self._h, c.ctypes.data), "sr_get_carry")
+        return c.reshape(n, 3)
+
+    def rate_table(self) -> np.ndarray:
+        r = np.zeros(10, dtype=np.uint32)
+        self._check(lib().sr_get_rate_table(self._h, r.ctypes.data), "sr_get_rate_table")
+        return r
+
+    def save(self) -> bytes:
+        n = C.c_size_t()
+        self._check(lib().sr_save(self._h, None, 0, C.byref(n)), "sr_save")
+        buf = C.create_string_buffer(n.value)
+        self._check(lib().sr_save(self._h, buf, n.value, C.byref(n)), "sr_save")
+        return buf.raw
+
+    @classmethod
+    def load(cls, blob: bytes, stream=None) -> "Sim":
+        h = C.c_void_p()
+        b = C.create_string_buffer(blob, len(blob))
+        rc = lib().sr_load(b, len(blob), _stream_ptr(stream), C.byref(h))
+        if rc != SR_OK:
+            raise SRError(rc, last_error(None))
+        return cls(_handle=h)
+
+
+def batch_run(sims: Sequence[Sim], stream=None) -> None:
+    """Run every simulation to its horizon in one persistent launch."""
+    arr = (C.c_void_p * len(sims))(*[s.handle for s in sims])
+    rc = lib().sr_batch_run(arr, len(sims), _stream_ptr(stream))
+    if rc != SR_OK:
+        raise SRError(rc, "sr_batch_run: " + last_error(sims[0].handle if sims else None))

@@ -1,0 +1,518 @@
+// sr_api.hip -- host runtime and C ABI of the synchronous-relaxation library
+// (declarations and contracts in include/sr.h).
+//
+// A simulation owns: the committed lattice and per-subdomain carry, each
+// double-buffered by window parity (the converged iteration writes the other
+// parity, so committing a window is a parity flip: nothing is copied); the
+// four boundary lists of every subdomain, double-buffered by iteration
+// parity (iteration r reads r-1's lists and writes its own); a per-subdomain
+// window event log; and one block of per-iteration flags.  The window loop of
+// Sec. 4 runs on the host: launch one relaxation iteration, read the 24-byte
+// flags, repeat until no boundary list changed, flip the window parity.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sr.h"
+#include "sr_internal.h"
+
+namespace sr {
+hipError_t launch_relax(const Lattice& L, const Step& st, hipStream_t stream);
+hipError_t launch_init_random(int8_t* s, int64_t n, uint64_t seed, hipStream_t stream);
+hipError_t launch_fill(int8_t* s, int64_t n, int8_t v, hipStream_t stream);
+hipError_t launch_observables(const int8_t* s, int Lx, int Ly, unsigned long long* out,
+                              hipStream_t stream);
+}  // namespace sr
+
+using namespace sr;
+
+struct sr_sim {
+  sr_params p;
+  Lattice L;
+  Step st;
+  hipStream_t stream = nullptr;
+  int64_t W = 0, H = 0;             // window and horizon in ticks
+  int64_t windows = 0, iterations = 0, events = 0;
+  int32_t last_g = 0, last_f = 0;
+  unsigned long long* obs = nullptr;   // device scratch for observables
+  IterFlags* hflags = nullptr;         // pinned host mirror of the flags
+  std::vector<std::vector<int64_t>> log_tick, log_site;   // SR_LOG_FULL
+  std::string err;
+};
+
+static std::string g_create_err;
+
+#define SR_FAIL(sim, code, ...)                                           \
+  do {                                                                    \
+    char _b[512];                                                         \
+    std::snprintf(_b, sizeof(_b), __VA_ARGS__);                           \
+    if (sim) (sim)->err = _b; else g_create_err = _b;                     \
+    return (code);                                                        \
+  } while (0)
+
+#define HIP_OR_FAIL(sim, call)                                            \
+  do {                                                                    \
+    hipError_t _e = (call);                                               \
+    if (_e != hipSuccess)                                                 \
+      SR_FAIL(sim, SR_EDEVICE, "%s failed: %s", #call, hipGetErrorString(_e)); \
+  } while (0)
+
+// ------------------------------------------------------------ parameters
+// llround of x * 2^tick_bits for x >= 0 (scaling by a power of two is exact).
+static int64_t to_ticks(double x, int tick_bits) {
+  return (int64_t)std::llround(std::ldexp(x, tick_bits));
+}
+
+// Class rates round(2^28 p_k), k = 5*[s=-1] + n_up; p from eq. pMin or
+// eq. pglauber with dE = 2 s (J (2 n_up - 4) + h) (eq. hamil, each bond once).
+static int rate_table(double J, double h, double T, int rule, uint32_t out[kClasses]) {
+  if (!(T > 0.0) || (rule != SR_METROPOLIS && rule != SR_GLAUBER)) return -1;
+  for (int k = 0; k < kClasses; ++k) {
+    int s = (k < 5) ? 1 : -1;
+    int nup = k % 5;
+    double x = -(2.0 * s * (J * (2 * nup - 4) + h)) / T;
+    double p;
+    if (rule == SR_METROPOLIS) {
+      double theta = std::exp(x);
+      p = theta < 1.0 ? theta : 1.0;
+    } else {
+      p = 1.0 / (1.0 + std::exp(-x));
+    }
+    double q = std::nearbyint(std::ldexp(p, kRateBits));
+    if (q > (double)kRateOne) q = (double)kRateOne;
+    out[k] = (uint32_t)q;
+  }
+  return 0;
+}
+
+static int sites_per_lane_shift(int nblk) {
+  int S = (nblk + 63) / 64, sh = 0;
+  while ((1 << sh) < S) sh++;
+  return sh;
+}
+
+static const char* check_block(int Lx, int Ly, int bx, int by) {
+  if (bx < 2 || by < 2 || bx > 64 || by > 64) return "bx and by must be in [2, 64]";
+  if (bx * by > 1024) return "bx*by must be <= 1024";
+  if (Lx % bx || Ly % by) return "Lx % bx and Ly % by must be 0";
+  int S = 1 << sites_per_lane_shift(bx * by);
+  if (S > 16 || bx % S) return "bx must be a multiple of the sites per lane";
+  return nullptr;
+}
+
+// ------------------------------------------------------------ tuner
+// Block: a fixed table (never load-dependent, since the block changes the
+// random streams and hence the trajectory).  Window: the step-size rule of
+// Sec. 5, T_max = log N / (lambda |dG_i|), times a factor that keeps the
+// expected boundary events per subdomain-window near a target; the window
+// does not change results, only iteration counts.
+extern "C" int sr_tune(const sr_params* p, int32_t* bx, int32_t* by, double* window) {
+  if (!p || p->Lx < 4 || p->Ly < 4) return SR_EINVAL;
+  int b = 16;
+  int minL = std::min(p->Lx, p->Ly);
+  if (minL >= 2048 && p->T <= 1.25) b = 32;   // sparse flips: amortise per-window cost
+  while (b > 2 && (p->Lx % b || p->Ly % b)) b >>= 1;
+  int tbx = b, tby = b;
+  if (check_block(p->Lx, p->Ly, tbx, tby)) return SR_EINVAL;
+  if (bx) *bx = tbx;
+  if (by) *by = tby;
+  if (window) {
+    double nsub = (double)(p->Lx / tbx) * (double)(p->Ly / tby);
+    double dG = 2.0 * (tbx + tby) - 4.0;
+    double tmax = std::log(std::max(nsub, 2.0)) / dG;
+    *window = std::min(std::max(4.0 * tmax, 0.125), 2.0);
+  }
+  return SR_OK;
+}
+
+// ------------------------------------------------------------ buffers
+static void free_hist(sr_sim* s) {
+  for (int q = 0; q < 2; ++q) {
+    if (s->L.hist[q]) (void)hipFree(s->L.hist[q]);
+    s->L.hist[q] = nullptr;
+  }
+  if (s->L.wlog) (void)hipFree(s->L.wlog);
+  s->L.wlog = nullptr;
+}
+
+static int alloc_hist(sr_sim* s) {
+  Lattice& L = s->L;
+  size_t nh = (size_t)L.nsub * kEdges * (size_t)L.hcap;
+  for (int q = 0; q < 2; ++q)
+    if (hipMalloc(&L.hist[q], nh * sizeof(uint64_t)) != hipSuccess)
+      SR_FAIL(s, SR_ENOMEM, "cannot allocate %zu boundary-list entries", nh);
+  if (hipMalloc(&L.wlog, (size_t)L.nsub * L.wcap * sizeof(uint64_t)) != hipSuccess)
+    SR_FAIL(s, SR_ENOMEM, "cannot allocate window logs");
+  return SR_OK;
+}
+
+static void free_all(sr_sim* s) {
+  Lattice& L = s->L;
+  free_hist(s);
+  for (int q = 0; q < 2; ++q) {
+    if (L.spins[q]) (void)hipFree(L.spins[q]);
+    if (L.carry[q]) (void)hipFree(L.carry[q]);
+    if (L.hcnt[q]) (void)hipFree(L.hcnt[q]);
+    L.spins[q] = nullptr; L.carry[q] = nullptr; L.hcnt[q] = nullptr;
+  }
+  if (L.wcnt) (void)hipFree(L.wcnt);
+  if (L.flags) (void)hipFree(L.flags);
+  if (s->obs) (void)hipFree(s->obs);
+  if (s->hflags) (void)hipHostFree(s->hflags);
+  L.wcnt = nullptr; L.flags = nullptr; s->obs = nullptr; s->hflags = nullptr;
+}
+
+static int create_impl(const sr_params* pin, void* stream, sr_sim** out, bool init_state) {
+  if (!pin || !out) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "null argument");
+  *out = nullptr;
+  sr_params p = *pin;
+  if (p.Lx < 4 || p.Ly < 4) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "Lx and Ly must be >= 4");
+  if (p.tick_bits == 0) p.tick_bits = 28;
+  if (p.tick_bits < 4 || p.tick_bits > 28) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "tick_bits must be in [4, 28]");
+  if (!(p.T > 0.0) || !std::isfinite(p.J) || !std::isfinite(p.h))
+    SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "need T > 0 and finite J, h");
+  if (p.rule != SR_METROPOLIS && p.rule != SR_GLAUBER) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "unknown rule");
+  if (!(p.horizon >= 0.0) || !std::isfinite(p.horizon)) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "horizon must be >= 0");
+  if (p.log_mode != SR_LOG_DIGEST && p.log_mode != SR_LOG_FULL) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "unknown log mode");
+  if (p.init == SR_INIT_USER && !p.init_spins) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "SR_INIT_USER needs init_spins");
+  if (p.init != SR_INIT_RANDOM && p.init != SR_INIT_ALL_UP && p.init != SR_INIT_USER)
+    SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "unknown init mode");
+  if (p.bx == 0 || p.by == 0 || p.window == 0.0) {
+    int32_t tbx, tby; double tw;
+    if (sr_tune(&p, &tbx, &tby, &tw) != SR_OK) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "tuner found no block");
+    if (p.bx == 0 || p.by == 0) { p.bx = tbx; p.by = tby; }
+    if (p.window == 0.0) p.window = tw;
+  }
+  if (const char* why = check_block(p.Lx, p.Ly, p.bx, p.by)) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "%s", why);
+  if (!(p.window > 0.0) || !std::isfinite(p.window)) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "window must be > 0");
+  int64_t W = to_ticks(p.window, p.tick_bits), H = to_ticks(p.horizon, p.tick_bits);
+  if (W < 1) W = 1;
+  if (H >= ((int64_t)1 << 46)) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "horizon too long for the tick grid");
+  if (p.max_iters <= 0) p.max_iters = 10000;
+  if (p.hist_cap < 0 || p.wlog_cap < 0) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "capacities must be >= 0");
+
+  sr_sim* s = new sr_sim();
+  s->p = p;
+  s->p.init_spins = nullptr;
+  s->stream = (hipStream_t)stream;
+  s->W = W; s->H = H;
+  Lattice& L = s->L;
+  std::memset(&L, 0, sizeof(L));
+  L.Lx = p.Lx; L.Ly = p.Ly; L.bx = p.bx; L.by = p.by;
+  L.nbx = p.Lx / p.bx; L.nby = p.Ly / p.by; L.nsub = L.nbx * L.nby;
+  L.sshift = sites_per_lane_shift(p.bx * p.by);
+  L.S = 1 << L.sshift;
+  L.tick_bits = p.tick_bits;
+  if (rate_table(p.J, p.h, p.T, p.rule, L.rate) != 0) { delete s; SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "bad rate parameters"); }
+  L.seed_lo = (uint32_t)p.seed; L.seed_hi = (uint32_t)(p.seed >> 32);
+  // capacities: at most one flip per site per time unit on average (every
+  // rate <= lambda = 1), plus six standard deviations
+  double wt = std::ldexp((double)W, -p.tick_bits);
+  double edge = std::max(p.bx, p.by) * wt, blk = (double)p.bx * p.by * wt;
+  L.hcap = (int)std::max(64.0, std::ceil((edge + 6.0 * std::sqrt(edge) + 16.0) / 64.0) * 64.0);
+  L.wcap = (int)std::max(64.0, std::ceil((blk + 6.0 * std::sqrt(blk) + 32.0) / 64.0) * 64.0);
+  if (p.hist_cap > 0) L.hcap = p.hist_cap;
+  if (p.wlog_cap > 0) L.wcap = p.wlog_cap;
+
+  size_t nsite = (size_t)p.Lx * p.Ly;
+  auto fail = [&](int code, const char* what) {
+    g_create_err = what;
+    free_all(s);
+    delete s;
+    return code;
+  };
+  for (int q = 0; q < 2; ++q) {
+    if (hipMalloc(&L.spins[q], nsite) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate lattice");
+    if (hipMalloc(&L.carry[q], (size_t)L.nsub * sizeof(Carry)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate carry");
+    if (hipMalloc(&L.hcnt[q], (size_t)L.nsub * kEdges * sizeof(uint32_t)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate list counts");
+  }
+  if (hipMalloc(&L.wcnt, (size_t)L.nsub * sizeof(uint32_t)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate log counts");
+  if (hipMalloc(&L.flags, sizeof(IterFlags)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate flags");
+  if (hipMalloc(&s->obs, 4 * sizeof(unsigned long long)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate scratch");
+  if (hipHostMalloc(&s->hflags, sizeof(IterFlags), hipHostMallocDefault) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate pinned flags");
+  if (alloc_hist(s) != SR_OK) return fail(SR_ENOMEM, "cannot allocate boundary lists");
+
+  if (init_state) {
+    hipError_t e = hipSuccess;
+    if (p.init == SR_INIT_RANDOM) e = launch_init_random(L.spins[0], (int64_t)nsite, p.seed, s->stream);
+    else if (p.init == SR_INIT_ALL_UP) e = launch_fill(L.spins[0], (int64_t)nsite, 1, s->stream);
+    else {
+      for (size_t i = 0; i < nsite; ++i)
+        if (pin->init_spins[i] != 1 && pin->init_spins[i] != -1) return fail(SR_EINVAL, "init_spins must be +1/-1");
+      e = hipMemcpyAsync(L.spins[0], pin->init_spins, nsite, hipMemcpyHostToDevice, s->stream);
+    }
+    if (e != hipSuccess) return fail(SR_EDEVICE, "initial spins failed");
+    if (hipMemsetAsync(L.carry[0], 0, (size_t)L.nsub * sizeof(Carry), s->stream) != hipSuccess)
+      return fail(SR_EDEVICE, "carry init failed");
+  }
+  if (hipStreamSynchronize(s->stream) != hipSuccess) return fail(SR_EDEVICE, "stream sync failed");
+  if (p.log_mode == SR_LOG_FULL) {
+    s->log_tick.resize(L.nsub);
+    s->log_site.resize(L.nsub);
+  }
+  s->st.t_c = 0; s->st.t_end = 0; s->st.wp = 0; s->st.it = 0;
+  *out = s;
+  return SR_OK;
+}
+
+extern "C" int sr_create(const sr_params* p, void* hip_stream, sr_sim** out) {
+  return create_impl(p, hip_stream, out, true);
+}
+
+extern "C" void sr_destroy(sr_sim* s) {
+  if (!s) return;
+  if (s->stream) (void)hipStreamSynchronize(s->stream); else (void)hipDeviceSynchronize();
+  free_all(s);
+  delete s;
+}
+
+extern "C" const char* sr_last_error(const sr_sim* s) {
+  return s ? s->err.c_str() : g_create_err.c_str();
+}
+
+// ------------------------------------------------------------ window loop
+static int grow(sr_sim* s, uint32_t ovf) {
+  Lattice& L = s->L;
+  if (ovf & 1u) {
+    if (L.hcap >= (1 << 20)) SR_FAIL(s, SR_EOVERFLOW, "boundary list capacity limit reached");
+    L.hcap *= 2;
+  }
+  if (ovf & 2u) {
+    if (L.wcap >= (1 << 22)) SR_FAIL(s, SR_EOVERFLOW, "window log capacity limit reached");
+    L.wcap *= 2;
+  }
+  free_hist(s);
+  return alloc_hist(s);
+}
+
+static int commit(sr_sim* s) {
+  Lattice& L = s->L;
+  if (s->p.log_mode == SR_LOG_FULL) {
+    std::vector<uint32_t> cnt(L.nsub);
+    std::vector<uint64_t> wl((size_t)L.nsub * L.wcap);
+    HIP_OR_FAIL(s, hipMemcpyAsync(cnt.data(), L.wcnt, cnt.size() * 4, hipMemcpyDeviceToHost, s->stream));
+    HIP_OR_FAIL(s, hipMemcpyAsync(wl.data(), L.wlog, wl.size() * 8, hipMemcpyDeviceToHost, s->stream));
+    HIP_OR_FAIL(s, hipStreamSynchronize(s->stream));
+    for (int d = 0; d < L.nsub; ++d) {
+      int x0 = (d % L.nbx) * L.bx, y0 = (d / L.nbx) * L.by;
+      for (uint32_t i = 0; i < cnt[d]; ++i) {
+        uint64_t e = wl[(size_t)d * L.wcap + i];
+        int v = (int)(e & 0xFFFF);
+        int ly = v / L.bx, lx = v % L.bx;
+        s->log_tick[d].push_back((int64_t)(e >> kPosBits));
+        s->log_site[d].push_back((int64_t)(y0 + ly) * L.Lx + x0 + lx);
+      }
+    }
+  }
+  s->st.wp ^= 1;
+  s->st.t_c = s->st.t_end;
+  s->windows++;
+  return SR_OK;
+}
+
+static int run_one_window(sr_sim* s, int32_t* g_out) {
+  Lattice& L = s->L;
+  s->st.t_end = std::min(s->st.t_c + s->W, s->H);
+  uint32_t fmax = 0;
+  for (int it = 0; it < s->p.max_iters; ++it) {
+    s->st.it = it;
+    HIP_OR_FAIL(s, hipMemsetAsync(L.flags, 0, sizeof(IterFlags), s->stream));
+    HIP_OR_FAIL(s, launch_relax(L, s->st, s->stream));
+    HIP_OR_FAIL(s, hipMemcpyAsync(s->hflags, L.flags, sizeof(IterFlags), hipMemcpyDeviceToHost, s->stream));
+    HIP_OR_FAIL(s, hipStreamSynchronize(s->stream));
+    IterFlags f = *s->hflags;
+    s->iterations++;
+    s->events += (int64_t)f.events;
+    if (f.overflow) {
+      int rc = grow(s, f.overflow);
+      if (rc != SR_OK) return rc;
+      it = -1;                     // re-run the window from its committed state
+      fmax = 0;
+      continue;
+    }
+    fmax = std::max(fmax, f.fmax);
+    if (!f.changed) {
+      s->last_g = it + 1;
+      s->last_f = (int32_t)fmax;
+      if (g_out) *g_out = it + 1;
+      return commit(s);
+    }
+  }
+  SR_FAIL(s, SR_ENOCONV, "window [%lld, %lld) did not converge in %d iterations",
+          (long long)s->st.t_c, (long long)s->st.t_end, s->p.max_iters);
+}
+
+extern "C" int sr_run_window(sr_sim* s, int32_t n_windows, int32_t* iters_out, int32_t* n_done) {
+  if (!s) return SR_EINVAL;
+  if (n_done) *n_done = 0;
+  int32_t done = 0;
+  while (n_windows < 0 || done < n_windows) {
+    if (s->st.t_c >= s->H) {
+      if (n_windows < 0 || done > 0) break;
+      SR_FAIL(s, SR_EDONE, "committed time already at the horizon");
+    }
+    int32_t g = 0;
+    int rc = run_one_window(s, &g);
+    if (rc != SR_OK) return rc;
+    if (iters_out) iters_out[done] = g;
+    done++;
+    if (n_done) *n_done = done;
+  }
+  return SR_OK;
+}
+
+// ------------------------------------------------------------ queries
+extern "C" int sr_observables(sr_sim* s, sr_obs* o) {
+  if (!s || !o) return SR_EINVAL;
+  Lattice& L = s->L;
+  unsigned long long h[2];
+  HIP_OR_FAIL(s, hipMemsetAsync(s->obs, 0, 2 * sizeof(unsigned long long), s->stream));
+  HIP_OR_FAIL(s, launch_observables(L.spins[s->st.wp], L.Lx, L.Ly, s->obs, s->stream));
+  HIP_OR_FAIL(s, hipMemcpyAsync(h, s->obs, sizeof(h), hipMemcpyDeviceToHost, s->stream));
+  std::vector<Carry> c(L.nsub);
+  HIP_OR_FAIL(s, hipMemcpyAsync(c.data(), L.carry[s->st.wp], c.size() * sizeof(Carry), hipMemcpyDeviceToHost, s->stream));
+  HIP_OR_FAIL(s, hipStreamSynchronize(s->stream));
+  std::memset(o, 0, sizeof(*o));
+  o->tick = s->st.t_c;
+  o->M = (int64_t)h[0];
+  o->bond_sum = (int64_t)h[1];
+  for (const Carry& x : c) o->flips += x.flips;
+  o->events_processed = s->events;
+  o->windows = s->windows;
+  o->iterations = s->iterations;
+  o->last_g = s->last_g;
+  o->last_f = s->last_f;
+  o->tick_bits = s->p.tick_bits;
+  o->n_sub = L.nsub;
+  o->bx = L.bx; o->by = L.by;
+  o->Lx = L.Lx; o->Ly = L.Ly;
+  o->window_ticks = s->W;
+  o->horizon_ticks = s->H;
+  return SR_OK;
+}
+
+extern "C" int sr_get_spins(sr_sim* s, int8_t* out) {
+  if (!s || !out) return SR_EINVAL;
+  HIP_OR_FAIL(s, hipMemcpyAsync(out, s->L.spins[s->st.wp], (size_t)s->L.Lx * s->L.Ly, hipMemcpyDeviceToHost, s->stream));
+  HIP_OR_FAIL(s, hipStreamSynchronize(s->stream));
+  return SR_OK;
+}
+
+extern "C" int sr_get_log(sr_sim* s, int32_t d, int64_t* ticks, int64_t* sites, int64_t cap, int64_t* n) {
+  if (!s || d < 0 || d >= s->L.nsub || !n) return SR_EINVAL;
+  if (s->p.log_mode != SR_LOG_FULL) SR_FAIL(s, SR_EINVAL, "event logs need SR_LOG_FULL");
+  const auto& t = s->log_tick[d];
+  const auto& v = s->log_site[d];
+  *n = (int64_t)t.size();
+  int64_t m = std::min<int64_t>(cap, (int64_t)t.size());
+  for (int64_t i = 0; i < m; ++i) {
+    if (ticks) ticks[i] = t[i];
+    if (sites) sites[i] = v[i];
+  }
+  return SR_OK;
+}
+
+static int fetch_carry(sr_sim* s, std::vector<Carry>& c) {
+  c.resize(s->L.nsub);
+  HIP_OR_FAIL(s, hipMemcpyAsync(c.data(), s->L.carry[s->st.wp], c.size() * sizeof(Carry), hipMemcpyDeviceToHost, s->stream));
+  HIP_OR_FAIL(s, hipStreamSynchronize(s->stream));
+  return SR_OK;
+}
+
+extern "C" int sr_get_digests(sr_sim* s, uint64_t* digests, int64_t* flips) {
+  if (!s) return SR_EINVAL;
+  std::vector<Carry> c;
+  int rc = fetch_carry(s, c);
+  if (rc) return rc;
+  for (int d = 0; d < s->L.nsub; ++d) {
+    if (digests) digests[d] = c[d].digest;
+    if (flips) flips[d] = c[d].flips;
+  }
+  return SR_OK;
+}
+
+extern "C" int sr_get_carry(sr_sim* s, int64_t* out) {
+  if (!s || !out) return SR_EINVAL;
+  std::vector<Carry> c;
+  int rc = fetch_carry(s, c);
+  if (rc) return rc;
+  for (int d = 0; d < s->L.nsub; ++d) {
+    out[3 * d + 0] = (int64_t)c[d].j;
+    out[3 * d + 1] = c[d].anchor;
+    out[3 * d + 2] = (int64_t)c[d].acc;
+  }
+  return SR_OK;
+}
+
+extern "C" int sr_get_rate_table(sr_sim* s, uint32_t out[10]) {
+  if (!s || !out) return SR_EINVAL;
+  std::memcpy(out, s->L.rate, sizeof(s->L.rate));
+  return SR_OK;
+}
+
+// ------------------------------------------------------------ checkpoint
+struct SaveHeader {
+  char magic[8];
+  sr_params p;
+  int64_t t_c, windows, iterations, events;
+  int32_t last_g, last_f;
+  int32_t nsub, pad;
+};
+
+extern "C" int sr_save(sr_sim* s, void* blob, size_t cap, size_t* n) {
+  if (!s || !n) return SR_EINVAL;
+  size_t nsite = (size_t)s->L.Lx * s->L.Ly;
+  size_t need = sizeof(SaveHeader) + nsite + (size_t)s->L.nsub * sizeof(Carry);
+  *n = need;
+  if (!blob) return SR_OK;
+  if (cap < need) SR_FAIL(s, SR_EINVAL, "checkpoint buffer too small (%zu < %zu)", cap, need);
+  SaveHeader h;
+  std::memset(&h, 0, sizeof(h));
+  std::memcpy(h.magic, "SRCKPT1", 8);
+  h.p = s->p;
+  h.p.init_spins = nullptr;
+  h.t_c = s->st.t_c; h.windows = s->windows; h.iterations = s->iterations; h.events = s->events;
+  h.last_g = s->last_g; h.last_f = s->last_f; h.nsub = s->L.nsub;
+  char* b = (char*)blob;
+  std::memcpy(b, &h, sizeof(h));
+  HIP_OR_FAIL(s, hipMemcpyAsync(b + sizeof(h), s->L.spins[s->st.wp], nsite, hipMemcpyDeviceToHost, s->stream));
+  HIP_OR_FAIL(s, hipMemcpyAsync(b + sizeof(h) + nsite, s->L.carry[s->st.wp], (size_t)s->L.nsub * sizeof(Carry), hipMemcpyDeviceToHost, s->stream));
+  HIP_OR_FAIL(s, hipStreamSynchronize(s->stream));
+  return SR_OK;
+}
+
+extern "C" int sr_load(const void* blob, size_t n, void* stream, sr_sim** out) {
+  if (!blob || !out || n < sizeof(SaveHeader)) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "bad checkpoint");
+  SaveHeader h;
+  std::memcpy(&h, blob, sizeof(h));
+  if (std::memcmp(h.magic, "SRCKPT1", 8) != 0) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "not a checkpoint");
+  size_t nsite = (size_t)h.p.Lx * h.p.Ly;
+  if (n < sizeof(h) + nsite + (size_t)h.nsub * sizeof(Carry)) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "truncated checkpoint");
+  int rc = create_impl(&h.p, stream, out, false);
+  if (rc != SR_OK) return rc;
+  sr_sim* s = *out;
+  if (s->L.nsub != h.nsub) { sr_destroy(s); *out = nullptr; SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "checkpoint does not match its parameters"); }
+  const char* b = (const char*)blob;
+  HIP_OR_FAIL(s, hipMemcpyAsync(s->L.spins[0], b + sizeof(h), nsite, hipMemcpyHostToDevice, s->stream));
+  HIP_OR_FAIL(s, hipMemcpyAsync(s->L.carry[0], b + sizeof(h) + nsite, (size_t)h.nsub * sizeof(Carry), hipMemcpyHostToDevice, s->stream));
+  HIP_OR_FAIL(s, hipStreamSynchronize(s->stream));
+  s->st.t_c = h.t_c; s->st.wp = 0;
+  s->windows = h.windows; s->iterations = h.iterations; s->events = h.events;
+  s->last_g = h.last_g; s->last_f = h.last_f;
+  return SR_OK;
+}
+
+// ------------------------------------------------------------ batch (stub until built)
+extern "C" int sr_batch_run(sr_sim* const* sims, int32_t n, void* stream) {
+  (void)stream;
+  for (int32_t i = 0; i < n; ++i) {
+    int rc = sr_run_window(sims[i], -1, nullptr, nullptr);
+    if (rc != SR_OK) return rc;
+  }
+  return SR_OK;
+}

@@ -1,0 +1,564 @@
+// sr_kernels.hip -- gfx950 kernels of the synchronous-relaxation library.
+//
+// One 64-lane wavefront plays one of the paper's PEs: it owns one bx x by
+// subdomain and, in one launch, produces that subdomain's history over the
+// current window [t_c, t_end) (Sec. 4 box, step (a); Sec. 5).  The kernel
+// boundary is the "synchronize" of steps (b)/(d); step (c) is done by every
+// wave comparing its own new boundary lists with the ones it produced in the
+// previous iteration (the neighbours' assumptions) and raising a change flag.
+//
+// Per-wave state lives in registers:
+//   * classes of the owned sites as 4-bit nibbles, lane l owning the S
+//     consecutive local sites [l*S, l*S + S) (row-major), so a wave-wide
+//     prefix over lanes visits sites in ascending local order (Sec. 3 "linear
+//     order" of a class);
+//   * class counts N_k and rates r_k in lanes 0..9, the cumulative weights
+//     C_k = sum_{i<=k} N_i r_i by a 16-lane DPP scan (eqs. biglambda, Wsum);
+//   * the halo spins as four 64-bit masks;
+//   * 64 presimulated (E, V) pairs, one per lane (Philox-4x32-10 + a fixed-point
+//     -ln), refilled every 64 events (the "presimulated list" of Sec. 4);
+//   * 64-entry chunks of the four neighbour boundary lists (break points of
+//     Sec. 5), of the four own lists of the previous iteration (for the
+//     comparison) and of the lists / event log being written (flushed with
+//     coalesced stores).
+// Nothing on the event chain touches HBM except chunk refills and flushes.
+#include "sr_internal.h"
+
+namespace sr {
+
+// ------------------------------------------------------------ wave helpers
+__device__ __forceinline__ int lane_id() {
+  return (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+__device__ __forceinline__ uint32_t rdl(uint32_t v, int l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+__device__ __forceinline__ uint64_t rdl64(uint64_t v, int l) {
+  return (uint64_t)rdl((uint32_t)v, l) | ((uint64_t)rdl((uint32_t)(v >> 32), l) << 32);
+}
+__device__ __forceinline__ int ctz64(uint64_t m) { return __builtin_ctzll(m); }
+__device__ __forceinline__ int64_t min64(int64_t a, int64_t b) { return a < b ? a : b; }
+
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ uint32_t dpp0(uint32_t x) {
+  // lanes whose DPP source is outside the row (or whose row is masked off)
+  // read 0
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWMASK, 0xf, false);
+}
+
+// Inclusive prefix sum of 32-bit values over the 64 lanes.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+  x += dpp0<0x111, 0xf>(x);  // row_shr:1
+  x += dpp0<0x112, 0xf>(x);  // row_shr:2
+  x += dpp0<0x114, 0xf>(x);  // row_shr:4
+  x += dpp0<0x118, 0xf>(x);  // row_shr:8
+  x += dpp0<0x142, 0xa>(x);  // row_bcast:15 into rows 1, 3
+  x += dpp0<0x143, 0xc>(x);  // row_bcast:31 into rows 2, 3
+  return x;
+}
+
+// Inclusive prefix sum of 64-bit values within each row of 16 lanes.
+template <int SH>
+__device__ __forceinline__ uint64_t row_step64(uint64_t x) {
+  uint32_t lo = dpp0<0x110 + SH, 0xf>((uint32_t)x);
+  uint32_t hi = dpp0<0x110 + SH, 0xf>((uint32_t)(x >> 32));
+  return x + (((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ uint64_t row_incl_scan64(uint64_t x) {
+  x = row_step64<1>(x);
+  x = row_step64<2>(x);
+  x = row_step64<4>(x);
+  x = row_step64<8>(x);
+  return x;
+}
+
+// ------------------------------------------------------------ random numbers
+// Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), written from its
+// published round function: multipliers 0xD2511F53 / 0xCD9E8D57, key
+// increments 0x9E3779B9 / 0xBB67AE85.
+__device__ __forceinline__ void philox4x32_10(uint32_t k0, uint32_t k1, uint32_t& c0,
+                                              uint32_t& c1, uint32_t& c2, uint32_t& c3) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+    uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+  }
+}
+
+// -ln(U), U = (u|1)/2^64, as an integer in units of 2^-(28+tick_bits):
+// binary logarithm of the normalised mantissa by 32 repeated squarings of a
+// truncated Q1.31 value, then one 64x64->128 product with floor(ln2 * 2^64).
+__device__ __forceinline__ uint64_t neglog_fixed(uint64_t u, int tick_bits) {
+  const uint64_t kLn2Q64 = 0xB17217F7D1CF79ABull;
+  uint64_t m = u | 1ull;
+  int c = __clzll((long long)m);
+  int e = 63 - c;
+  uint32_t z = (uint32_t)((m << c) >> 32);
+  uint32_t frac = 0;
+#pragma unroll 8
+  for (int i = 0; i < 32; ++i) {
+    uint64_t q = (uint64_t)z * (uint64_t)z;
+    uint32_t bit = (uint32_t)(q >> 63);
+    frac = (frac << 1) | bit;
+    z = (uint32_t)(q >> (31 + bit));
+  }
+  uint64_t lq = ((uint64_t)(64 - e) << 32) - (uint64_t)frac;
+  uint64_t lo = lq * kLn2Q64, hi = __umul64hi(lq, kLn2Q64);
+  int sh = 96 - (kRateBits + tick_bits);  // 40 .. 64
+  return sh >= 64 ? (hi >> (sh - 64)) : ((hi << (64 - sh)) | (lo >> sh));
+}
+
+// The 64 pairs (E_j, V_j), j = j0 + lane, of subdomain d.
+__device__ __forceinline__ void draw_chunk(uint32_t k0, uint32_t k1, uint64_t j0, uint32_t d,
+                                           int lane, int tick_bits, uint64_t& E, uint64_t& V) {
+  uint64_t j = j0 + (uint64_t)lane;
+  uint32_t c0 = (uint32_t)j, c1 = (uint32_t)(j >> 32), c2 = d, c3 = 0;
+  philox4x32_10(k0, k1, c0, c1, c2, c3);
+  V = (uint64_t)c2 | ((uint64_t)c3 << 32);
+  E = neglog_fixed((uint64_t)c0 | ((uint64_t)c1 << 32), tick_bits);
+}
+
+// ------------------------------------------------------------ integer time
+// floor(n / d) and ceil(n / d) for d >= 1, exact when the quotient is below
+// 2^50 (a double estimate, then one correction step); larger quotients are
+// reported as 2^50, which callers treat as "beyond any horizon".
+__device__ __forceinline__ uint64_t udiv_floor(uint64_t n, uint64_t d, uint64_t* rem_nonzero) {
+  double qd = (double)n / (double)d;
+  if (qd >= 1125899906842624.0) { *rem_nonzero = 1; return 1ull << 50; }
+  uint64_t q = (uint64_t)qd;
+  uint64_t p = q * d;
+  if (p > n) { q -= 1; p -= d; }
+  else if (n - p >= d) { q += 1; p += d; }
+  *rem_nonzero = (n != p);
+  return q;
+}
+
+// Tick of the pending event: anchor + max(1, ceil((E - acc) / lam)), or never
+// when lam = 0 (eq. nextau, and eq. lambdataua after a break point).
+__device__ __forceinline__ int64_t next_tick(int64_t anchor, uint64_t E, uint64_t acc, uint64_t lam) {
+  if (lam == 0) return kTickInf;
+  uint64_t nz;
+  uint64_t q = udiv_floor(E - acc, lam, &nz);
+  if (q >= (1ull << 50)) return kTickInf;
+  q += nz;
+  if (q < 1) q = 1;
+  return anchor + (int64_t)q;
+}
+
+// ------------------------------------------------------------ lists
+// A 64-entry window onto a sorted boundary list in HBM.
+struct ListIn {
+  const uint64_t* p;
+  int n, head;
+  uint64_t chunk;
+  int64_t ht;          // tick of the head entry, kTickInf when exhausted
+};
+__device__ __forceinline__ void list_open(ListIn& s, const uint64_t* p, int n, int lane) {
+  s.p = p; s.n = n; s.head = 0;
+  s.chunk = (lane < n) ? p[lane] : ~0ull;
+  s.ht = n > 0 ? (int64_t)(rdl64(s.chunk, 0) >> kPosBits) : kTickInf;
+}
+// Returns the head entry and advances.
+__device__ __forceinline__ uint64_t list_pop(ListIn& s, int lane) {
+  uint64_t e = rdl64(s.chunk, s.head & 63);
+  s.head++;
+  if (s.head >= s.n) {
+    s.ht = kTickInf;
+  } else {
+    if ((s.head & 63) == 0) s.chunk = (s.head + lane < s.n) ? s.p[s.head + lane] : ~0ull;
+    s.ht = (int64_t)(rdl64(s.chunk, s.head & 63) >> kPosBits);
+  }
+  return e;
+}
+
+// An own boundary list being written: buffered 64 entries at a time, and
+// compared entry by entry with the same list of the previous iteration.
+struct ListOut {
+  uint64_t* p;
+  int cap, n;
+  uint64_t buf;
+  ListIn prev;
+  bool diff;
+};
+__device__ __forceinline__ void out_open(ListOut& o, uint64_t* p, int cap, const uint64_t* prev,
+                                         int nprev, int lane) {
+  o.p = p; o.cap = cap; o.n = 0; o.buf = 0; o.diff = false;
+  list_open(o.prev, prev, nprev, lane);
+}
+__device__ __forceinline__ void out_push(ListOut& o, uint64_t x, int lane) {
+  int k = o.n & 63;
+  if (lane == k) o.buf = x;
+  if (o.n < o.prev.n) {
+    if (list_pop(o.prev, lane) != x) o.diff = true;
+  } else {
+    o.diff = true;
+  }
+  o.n++;
+  if ((o.n & 63) == 0) {
+    int at = o.n - 64 + lane;
+    if (at < o.cap) o.p[at] = o.buf;
+  }
+}
+__device__ __forceinline__ void out_close(ListOut& o, int lane) {
+  int k = o.n & 63;
+  int at = o.n - k + lane;
+  if (lane < k && at < o.cap) o.p[at] = o.buf;
+  if (o.n != o.prev.n) o.diff = true;
+}
+
+// SplitMix64 finaliser (Steele, Lea & Flood 2014) for event digests.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
+  for (int off = 32; off >= 1; off >>= 1) {
+    uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, off, 64);
+    uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), off, 64);
+    x += ((uint64_t)hi << 32) | lo;
+  }
+  return x;
+}
+
+// ------------------------------------------------------------ relaxation
+// One subdomain (this wave) over one window, one iteration.
+__device__ __forceinline__ void relax_subdomain(const Lattice& L, const Step& st, int d,
+                                                int8_t* tile) {
+  const int lane = lane_id();
+  const int bx = L.bx, by = L.by, sh = L.sshift, S = 1 << sh;
+  const int nbx = L.nbx, nby = L.nby;
+  const int cx = d % nbx, cy = d / nbx;
+  const int x0 = cx * bx, y0 = cy * by;
+  const int nblk = bx * by;
+  const bool wrapx = (nbx == 1), wrapy = (nby == 1);
+  const int first = (st.it == 0);
+  const int pin = (st.it + 1) & 1, pout = st.it & 1;
+  const int hcap = L.hcap;
+  const int8_t* sp = L.spins[st.wp];
+  const int tw = bx + 2;
+
+  // committed block + one-site halo -> LDS (internal wrap falls out of the
+  // periodic global index when the block spans the torus)
+  for (int i = lane; i < (by + 2) * tw; i += 64) {
+    int ty = i / tw, tx = i - ty * tw;
+    int gy = y0 + ty - 1, gx = x0 + tx - 1;
+    gy = gy < 0 ? gy + L.Ly : (gy >= L.Ly ? gy - L.Ly : gy);
+    gx = gx < 0 ? gx + L.Lx : (gx >= L.Lx ? gx - L.Lx : gx);
+    tile[i] = sp[(int64_t)gy * L.Lx + gx];
+  }
+  __syncthreads();
+
+  // classes of owned sites, 4 bits each; unused nibbles hold 0xF
+  uint64_t cls = ~0ull;
+  const int base = lane << sh;
+  for (int i = 0; i < S; ++i) {
+    int v = base + i;
+    if (v < nblk) {
+      int ly = v / bx, lx = v - ly * bx;
+      int tp = (ly + 1) * tw + lx + 1;
+      int up = (tile[tp - 1] > 0) + (tile[tp + 1] > 0) + (tile[tp - tw] > 0) + (tile[tp + tw] > 0);
+      int k = (tile[tp] < 0 ? 5 : 0) + up;
+      cls = (cls & ~(0xFull << (4 * i))) | ((uint64_t)k << (4 * i));
+    }
+  }
+  // halo spins (bit p set = up) of the four external directions
+  uint64_t hN = ballot(lane < bx && tile[lane + 1] > 0);
+  uint64_t hS = ballot(lane < bx && tile[(by + 1) * tw + lane + 1] > 0);
+  uint64_t hW = ballot(lane < by && tile[(lane + 1) * tw] > 0);
+  uint64_t hE = ballot(lane < by && tile[(lane + 1) * tw + bx + 1] > 0);
+
+  // class counts N_k in lane k
+  uint32_t ncnt = 0;
+  for (int k = 0; k < kClasses; ++k) {
+    uint64_t x = cls ^ (0x1111111111111111ull * (uint64_t)k);
+    uint64_t nz = (x | (x >> 1) | (x >> 2) | (x >> 3)) & 0x1111111111111111ull;
+    uint32_t c = (uint32_t)__popcll(~nz & 0x1111111111111111ull);
+    uint32_t tot = rdl(wave_incl_scan(c), 63);
+    if (lane == k) ncnt = tot;
+  }
+  uint32_t rate = 0;
+#pragma unroll
+  for (int k = 0; k < kClasses; ++k)
+    if (lane == k) rate = L.rate[k];
+
+  // carry at committed time, presimulated randoms
+  const Carry* cin = &L.carry[st.wp][d];
+  uint64_t j = cin->j, acc = cin->acc;
+  int64_t anchor = cin->anchor;
+  const uint32_t k0 = L.seed_lo, k1 = L.seed_hi;
+  uint64_t Eb, Vb;
+  draw_chunk(k0, k1, j & ~63ull, (uint32_t)d, lane, L.tick_bits, Eb, Vb);
+  uint64_t E = rdl64(Eb, (int)(j & 63)), V = rdl64(Vb, (int)(j & 63));
+
+  uint64_t C = row_incl_scan64((uint64_t)ncnt * rate);
+  uint64_t lam = rdl64(C, kClasses - 1);
+  int64_t next = next_tick(anchor, E, acc, lam);
+
+  // neighbour histories of the previous iteration (break points);
+  // the first iteration assumes none (canonical assumption)
+  const int dn = ((cy + nby - 1) % nby) * nbx + cx;
+  const int ds = ((cy + 1) % nby) * nbx + cx;
+  const int dw = cy * nbx + (cx + nbx - 1) % nbx;
+  const int de = cy * nbx + (cx + 1) % nbx;
+  const uint64_t* hin = L.hist[pin];
+  const uint32_t* cin_n = L.hcnt[pin];
+  auto clampn = [&](uint32_t n) { return (int)(n < (uint32_t)hcap ? n : (uint32_t)hcap); };
+  ListIn inN, inS, inW, inE;
+  list_open(inN, hin + ((size_t)dn * kEdges + kS) * hcap, (first || wrapy) ? 0 : clampn(cin_n[dn * kEdges + kS]), lane);
+  list_open(inS, hin + ((size_t)ds * kEdges + kN) * hcap, (first || wrapy) ? 0 : clampn(cin_n[ds * kEdges + kN]), lane);
+  list_open(inW, hin + ((size_t)dw * kEdges + kE) * hcap, (first || wrapx) ? 0 : clampn(cin_n[dw * kEdges + kE]), lane);
+  list_open(inE, hin + ((size_t)de * kEdges + kW) * hcap, (first || wrapx) ? 0 : clampn(cin_n[de * kEdges + kW]), lane);
+
+  // own lists of this iteration, compared with those of the previous one
+  uint64_t* hout = L.hist[pout];
+  ListOut oN, oS, oW, oE;
+  out_open(oN, hout + ((size_t)d * kEdges + kN) * hcap, hcap, hin + ((size_t)d * kEdges + kN) * hcap, first ? 0 : clampn(cin_n[d * kEdges + kN]), lane);
+  out_open(oS, hout + ((size_t)d * kEdges + kS) * hcap, hcap, hin + ((size_t)d * kEdges + kS) * hcap, first ? 0 : clampn(cin_n[d * kEdges + kS]), lane);
+  out_open(oW, hout + ((size_t)d * kEdges + kW) * hcap, hcap, hin + ((size_t)d * kEdges + kW) * hcap, first ? 0 : clampn(cin_n[d * kEdges + kW]), lane);
+  out_open(oE, hout + ((size_t)d * kEdges + kE) * hcap, hcap, hin + ((size_t)d * kEdges + kE) * hcap, first ? 0 : clampn(cin_n[d * kEdges + kE]), lane);
+
+  // window event log (tick << 16 | local site), buffered 64 at a time
+  uint64_t* wl = L.wlog + (size_t)d * L.wcap;
+  const int wcap = L.wcap;
+  uint64_t lbuf = 0, dsum = 0;
+  int nev = 0, nbound = 0;
+  auto log_flush = [&](int k) {          // k buffered entries in lanes 0..k-1
+    int at = nev - k + lane;
+    if (lane < k) {
+      if (at < wcap) wl[at] = lbuf;
+      int v = (int)(lbuf & 0xFFFF);
+      int ly = v / bx, lx = v - ly * bx;
+      int64_t g = (int64_t)(y0 + ly) * L.Lx + x0 + lx;
+      dsum += mix64(mix64(lbuf >> kPosBits) + (uint64_t)g);
+    }
+  };
+
+  // move site u (local) by `delta` classes
+  auto change = [&](int u, int delta) {
+    int o = u >> sh, sl = (u & (S - 1)) * 4;
+    uint64_t w = rdl64(cls, o);
+    int a = (int)((w >> sl) & 15);
+    int b = a + delta;
+    if (lane == o) cls += (uint64_t)(int64_t)delta * (1ull << sl);
+    ncnt += (uint32_t)((lane == b) - (lane == a));
+  };
+
+  const int64_t t_end = st.t_end;
+  // hard bound on the loop: a window log far beyond its capacity means the
+  // window is re-run with more room anyway
+  const int nev_limit = 4 * wcap + 64;
+  bool runaway = false;
+  for (;;) {
+    if (nev >= nev_limit) { runaway = true; break; }
+    int64_t tb = min64(min64(inN.ht, inS.ht), min64(inW.ht, inE.ht));
+    if (next <= tb) {
+      // ---- own event (first on a tie: it chooses from the pre-tick state)
+      if (next >= t_end) break;
+      const int64_t t = next;
+      // class: first k with C_k > target (eqs. Wsum, Wstop)
+      uint64_t target = __umul64hi(V, lam);
+      uint64_t gt = ballot(lane < kClasses && C > target);
+      int ks = ctz64(gt);
+      uint64_t below = ks ? rdl64(C, ks - 1) : 0ull;
+      uint32_t rk = rdl(rate, ks);
+      uint64_t nzr;
+      uint32_t idx = (uint32_t)udiv_floor(target - below, rk, &nzr);
+      // site: the idx-th member of class ks in ascending local order
+      // (eqs. nores, vindex)
+      uint64_t x = cls ^ (0x1111111111111111ull * (uint64_t)ks);
+      uint64_t nz = (x | (x >> 1) | (x >> 2) | (x >> 3)) & 0x1111111111111111ull;
+      uint64_t mm = ~nz & 0x1111111111111111ull;
+      uint32_t cnt = (uint32_t)__popcll(mm);
+      uint32_t incl = wave_incl_scan(cnt);
+      uint32_t excl = incl - cnt;
+      int o = ctz64(ballot(excl <= idx && idx < incl));
+      uint32_t nth = idx - excl;
+      int pos = 0;
+      uint32_t c = (uint32_t)__popcll(mm & 0xFFFFFFFFull);
+      if (nth >= c) { nth -= c; pos = 32; }
+      c = (uint32_t)__popcll((mm >> pos) & 0xFFFFull);
+      if (nth >= c) { nth -= c; pos += 16; }
+      c = (uint32_t)__popcll((mm >> pos) & 0xFFull);
+      if (nth >= c) { nth -= c; pos += 8; }
+      c = (uint32_t)__popcll((mm >> pos) & 0xFull);
+      if (nth >= c) { pos += 4; }
+      const int v = (o << sh) + (int)rdl((uint32_t)(pos >> 2), o);
+      // flip v and re-class it and its in-block neighbours (Sec. 3, O(1))
+      const int ly = v / bx, lx = v - ly * bx;
+      const int kv = (int)((rdl64(cls, v >> sh) >> ((v & (S - 1)) * 4)) & 15);
+      const bool now_up = kv >= 5;
+      change(v, now_up ? -5 : 5);
+      const int dup = now_up ? 1 : -1;
+      if (lx > 0) change(v - 1, dup); else if (wrapx) change(v + bx - 1, dup);
+      if (lx < bx - 1) change(v + 1, dup); else if (wrapx) change(v - bx + 1, dup);
+      if (ly > 0) change(v - bx, dup); else if (wrapy) change(v + (by - 1) * bx, dup);
+      if (ly < by - 1) change(v + bx, dup); else if (wrapy) change(v - (by - 1) * bx, dup);
+      // record
+      const uint64_t tk = (uint64_t)t << kPosBits;
+      if (lane == (nev & 63)) lbuf = tk | (uint64_t)v;
+      nev++;
+      if ((nev & 63) == 0) log_flush(64);
+      bool onb = false;
+      if (!wrapy && ly == 0) { out_push(oN, tk | (uint64_t)lx, lane); onb = true; }
+      if (!wrapy && ly == by - 1) { out_push(oS, tk | (uint64_t)lx, lane); onb = true; }
+      if (!wrapx && lx == 0) { out_push(oW, tk | (uint64_t)ly, lane); onb = true; }
+      if (!wrapx && lx == bx - 1) { out_push(oE, tk | (uint64_t)ly, lane); onb = true; }
+      nbound += onb;
+      // next pair from the presimulated list
+      j += 1; anchor = t; acc = 0;
+      if ((j & 63) == 0) draw_chunk(k0, k1, j, (uint32_t)d, lane, L.tick_bits, Eb, Vb);
+      E = rdl64(Eb, (int)(j & 63)); V = rdl64(Vb, (int)(j & 63));
+      C = row_incl_scan64((uint64_t)ncnt * rate);
+      lam = rdl64(C, kClasses - 1);
+      next = next_tick(anchor, E, acc, lam);
+    } else {
+      // ---- break point: a neighbour flip changes our halo (Sec. 5)
+      if (tb >= t_end) break;
+      const int64_t t = tb;
+      if (inN.ht == tb) {
+        int p = (int)(list_pop(inN, lane) & 0xFFFF);
+        hN ^= 1ull << p;
+        change(p, ((hN >> p) & 1) ? 1 : -1);
+      } else if (inS.ht == tb) {
+        int p = (int)(list_pop(inS, lane) & 0xFFFF);
+        hS ^= 1ull << p;
+        change((by - 1) * bx + p, ((hS >> p) & 1) ? 1 : -1);
+      } else if (inW.ht == tb) {
+        int p = (int)(list_pop(inW, lane) & 0xFFFF);
+        hW ^= 1ull << p;
+        change(p * bx, ((hW >> p) & 1) ? 1 : -1);
+      } else {
+        int p = (int)(list_pop(inE, lane) & 0xFFFF);
+        hE ^= 1ull << p;
+        change(p * bx + bx - 1, ((hE >> p) & 1) ? 1 : -1);
+      }
+      // integrate the hazard up to the break point with the old rate
+      // (eqs. lambdataua, breaksum, bsubk), then re-aim with the new one
+      acc += lam * (uint64_t)(t - anchor);
+      anchor = t;
+      C = row_incl_scan64((uint64_t)ncnt * rate);
+      lam = rdl64(C, kClasses - 1);
+      next = next_tick(anchor, E, acc, lam);
+    }
+  }
+  if (nev & 63) log_flush(nev & 63);
+  out_close(oN, lane); out_close(oS, lane); out_close(oW, lane); out_close(oE, lane);
+
+  // end-of-window block -> working lattice (the other window parity)
+  int8_t* so = L.spins[st.wp ^ 1];
+  for (int i = 0; i < S; ++i) {
+    int v = base + i;
+    if (v < nblk) {
+      int ly = v / bx, lx = v - ly * bx;
+      int k = (int)((cls >> (4 * i)) & 15);
+      so[(int64_t)(y0 + ly) * L.Lx + x0 + lx] = (int8_t)(k < 5 ? 1 : -1);
+    }
+  }
+  uint64_t dtot = wave_sum64(dsum);
+  uint32_t* cnt_out = L.hcnt[pout] + d * kEdges;
+  if (lane == 0) {
+    cnt_out[kN] = (uint32_t)oN.n; cnt_out[kS] = (uint32_t)oS.n;
+    cnt_out[kW] = (uint32_t)oW.n; cnt_out[kE] = (uint32_t)oE.n;
+    Carry* co = &L.carry[st.wp ^ 1][d];
+    co->j = j; co->anchor = anchor; co->acc = acc;
+    co->digest = cin->digest + dtot;
+    co->flips = cin->flips + nev;
+    co->wflips = nev;
+    L.wcnt[d] = (uint32_t)nev;
+    bool changed = oN.diff || oS.diff || oW.diff || oE.diff;
+    uint32_t ovf = ((oN.n > hcap || oS.n > hcap || oW.n > hcap || oE.n > hcap) ? 1u : 0u) |
+                   ((nev > wcap || runaway) ? 2u : 0u);
+    if (changed) atomicOr(&L.flags->changed, 1u);
+    if (ovf) atomicOr(&L.flags->overflow, ovf);
+    atomicMax(&L.flags->fmax, (uint32_t)nbound);
+    atomicAdd(&L.flags->events, (unsigned long long)nev);
+  }
+}
+
+__global__ __launch_bounds__(64) void relax_kernel(Lattice L, Step st) {
+  extern __shared__ int8_t tile[];
+  const int d = blockIdx.x;
+  if (d >= L.nsub) return;
+  relax_subdomain(L, st, d, tile);
+}
+
+// ------------------------------------------------------------ init / observables
+__global__ void init_random_kernel(int8_t* s, int64_t n, uint32_t k0, uint32_t k1) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t c0 = (uint32_t)i, c1 = (uint32_t)((uint64_t)i >> 32), c2 = 0, c3 = 1;
+    philox4x32_10(k0, k1, c0, c1, c2, c3);
+    s[i] = (c0 & 1u) ? (int8_t)1 : (int8_t)-1;
+  }
+}
+
+__global__ void fill_kernel(int8_t* s, int64_t n, int8_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    s[i] = v;
+}
+
+// out[0] += sum s, out[1] += sum s (s_right + s_down)
+__global__ __launch_bounds__(256) void observables_kernel(const int8_t* s, int Lx, int Ly,
+                                                          unsigned long long* out) {
+  int64_t n = (int64_t)Lx * Ly;
+  long long m = 0, b = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int y = (int)(i / Lx), x = (int)(i - (int64_t)y * Lx);
+    int v = s[i];
+    int r = s[(int64_t)y * Lx + (x + 1 == Lx ? 0 : x + 1)];
+    int dn = s[(int64_t)(y + 1 == Ly ? 0 : y + 1) * Lx + x];
+    m += v;
+    b += v * (r + dn);
+  }
+  for (int off = 32; off >= 1; off >>= 1) {
+    m += __shfl_xor(m, off, 64);
+    b += __shfl_xor(b, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(&out[0], (unsigned long long)m);
+    atomicAdd(&out[1], (unsigned long long)b);
+  }
+}
+
+// ------------------------------------------------------------ launchers
+hipError_t launch_relax(const Lattice& L, const Step& st, hipStream_t stream) {
+  size_t lds = (size_t)(L.bx + 2) * (L.by + 2);
+  lds = (lds + 15) & ~(size_t)15;
+  hipLaunchKernelGGL(relax_kernel, dim3(L.nsub), dim3(64), lds, stream, L, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_random(int8_t* s, int64_t n, uint64_t seed, hipStream_t stream) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(init_random_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, s, n,
+                     (uint32_t)seed, (uint32_t)(seed >> 32));
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(int8_t* s, int64_t n, int8_t v, hipStream_t stream) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, s, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_observables(const int8_t* s, int Lx, int Ly, unsigned long long* out,
+                              hipStream_t stream) {
+  int64_t n = (int64_t)Lx * Ly;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(observables_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, s, Lx, Ly,
+                     out);
+  return hipGetLastError();
+}
+
+}  // namespace sr

@@ -1,0 +1,58 @@
+"""The C ABI library loads and exports every symbol include/sr.h declares;
+parameter validation runs on the host (no device work, no GPU needed)."""
+import re
+import os
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "sr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sr_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_cs_0405053_amd as sr
+    lib = sr.lib()
+    declared = _declared()
+    assert "sr_create" in declared and "sr_run_window" in declared
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(sr.EXPORTS) == declared
+
+
+@pytest.mark.parametrize("bad", [
+    dict(bx=7),                  # does not divide Lx
+    dict(bx=1, by=1),            # blocks too small
+    dict(T=0.0),
+    dict(tick_bits=40),
+    dict(horizon=-1.0),
+    dict(rule=5),
+    dict(window=-1.0),
+    dict(Lx=2, Ly=2, bx=2, by=2),
+    dict(bx=32, by=48, Ly=96),   # bx*by > 1024
+    dict(Lx=128, bx=128, by=4),  # bx > 64
+    dict(init="user"),           # no spins given
+])
+def test_invalid_parameters_rejected(bad):
+    import paper_cs_0405053_amd as sr
+    p = dict(Lx=64, Ly=64, bx=16, by=16, T=1.5, h=0.0, window=1.0, horizon=5.0, seed=1)
+    p.update(bad)
+    if p.get("rule") == 5:
+        p["rule"] = 1
+        p["T"] = -1.0
+    with pytest.raises(sr.SRError) as e:
+        sr.Sim(p)
+    assert e.value.code == sr.SR_EINVAL
+
+
+def test_tuner_block_is_deterministic_and_valid():
+    import paper_cs_0405053_amd as sr
+    for L in (32, 48, 64, 96, 512, 1024, 2048, 4096):
+        for T in (1.0, 2.0, 3.5):
+            bx, by, w = sr.tune(dict(Lx=L, Ly=L, T=T, horizon=10.0))
+            assert L % bx == 0 and L % by == 0 and w > 0
+            assert (bx, by, w) == sr.tune(dict(Lx=L, Ly=L, T=T, horizon=10.0))
