@@ -104,6 +104,9 @@ typedef struct {
   int32_t Lx, Ly;            /* lattice */
   int64_t window_ticks;      /* window in use */
   int64_t horizon_ticks;
+  int64_t relax_launches;    /* relaxation-kernel launches so far */
+  double relax_ms;           /* their summed device time (HIP events on the
+                                simulation's stream), milliseconds */
 } sr_obs;
 
 typedef struct sr_sim sr_sim;
@@ -124,6 +127,10 @@ int sr_run_window(sr_sim* s, int32_t n_windows, int32_t* iters_out, int32_t* n_d
 
 /* Observables at committed time (eq. hamil parts): M, bond sum, counters. */
 int sr_observables(sr_sim* s, sr_obs* out);
+
+/* Return to time 0: initial spins again (random, all up, or the spins given
+ * at creation), empty carry, counters cleared; keeps every allocation. */
+int sr_reset(sr_sim* s);
 
 /* Release everything.  NULL-safe. */
 void sr_destroy(sr_sim* s);

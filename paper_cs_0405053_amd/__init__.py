@@ -32,7 +32,7 @@ _LOG = {"digest": 0, "full": 1, 0: 0, 1: 1}
 # every function the C ABI exports (include/sr.h)
 EXPORTS = ["sr_create", "sr_run_window", "sr_observables", "sr_destroy", "sr_get_spins",
            "sr_get_log", "sr_get_digests", "sr_get_carry", "sr_get_rate_table", "sr_save",
-           "sr_load", "sr_last_error", "sr_batch_run", "sr_tune"]
+           "sr_load", "sr_last_error", "sr_batch_run", "sr_tune", "sr_reset"]
 
 
 class SRError(RuntimeError):
@@ -56,7 +56,8 @@ class Obs(C.Structure):
                 ("iterations", C.c_int64), ("last_g", C.c_int32), ("last_f", C.c_int32),
                 ("tick_bits", C.c_int32), ("n_sub", C.c_int32), ("bx", C.c_int32),
                 ("by", C.c_int32), ("Lx", C.c_int32), ("Ly", C.c_int32),
-                ("window_ticks", C.c_int64), ("horizon_ticks", C.c_int64)]
+                ("window_ticks", C.c_int64), ("horizon_ticks", C.c_int64),
+                ("relax_launches", C.c_int64), ("relax_ms", C.c_double)]
 
 
 _lib = None
@@ -86,6 +87,7 @@ def lib() -> C.CDLL:
         L.sr_last_error.argtypes = [P]
         L.sr_last_error.restype = C.c_char_p
         L.sr_batch_run.argtypes = [P, C.c_int32, P]
+        L.sr_reset.argtypes = [P]
         L.sr_tune.argtypes = [C.POINTER(Params), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                               C.POINTER(C.c_double)]
         _lib = L
@@ -193,6 +195,10 @@ class Sim:
                                  C.byref(done))
         self._check(rc, "sr_run_window")
         return g[:done.value].copy()
+
+    def reset(self) -> None:
+        """Back to time 0 with the initial spins; keeps all allocations."""
+        self._check(lib().sr_reset(self._h), "sr_reset")
 
     def observables(self) -> Dict:
         o = Obs()

@@ -40,6 +40,10 @@ struct sr_sim {
   int64_t windows = 0, iterations = 0, events = 0;
   int32_t last_g = 0, last_f = 0;
   unsigned long long* obs = nullptr;   // device scratch for observables
+  int8_t* init_copy = nullptr;         // initial spins for sr_reset (SR_INIT_USER)
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  int64_t relax_launches = 0;
+  double relax_ms = 0.0;
   IterFlags* hflags = nullptr;         // pinned host mirror of the flags
   std::vector<std::vector<int64_t>> log_tick, log_site;   // SR_LOG_FULL
   std::string err;
@@ -164,6 +168,10 @@ static void free_all(sr_sim* s) {
   if (L.flags) (void)hipFree(L.flags);
   if (s->obs) (void)hipFree(s->obs);
   if (s->hflags) (void)hipHostFree(s->hflags);
+  if (s->init_copy) (void)hipFree(s->init_copy);
+  if (s->ev0) (void)hipEventDestroy(s->ev0);
+  if (s->ev1) (void)hipEventDestroy(s->ev1);
+  s->init_copy = nullptr; s->ev0 = nullptr; s->ev1 = nullptr;
   L.wcnt = nullptr; L.flags = nullptr; s->obs = nullptr; s->hflags = nullptr;
 }
 
@@ -236,6 +244,11 @@ static int create_impl(const sr_params* pin, void* stream, sr_sim** out, bool in
   if (hipMalloc(&s->obs, 4 * sizeof(unsigned long long)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate scratch");
   if (hipHostMalloc(&s->hflags, sizeof(IterFlags), hipHostMallocDefault) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate pinned flags");
   if (alloc_hist(s) != SR_OK) return fail(SR_ENOMEM, "cannot allocate boundary lists");
+  if (hipEventCreate(&s->ev0) != hipSuccess || hipEventCreate(&s->ev1) != hipSuccess)
+    return fail(SR_EDEVICE, "cannot create events");
+  if (p.init == SR_INIT_USER && init_state) {
+    if (hipMalloc(&s->init_copy, nsite) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate initial spins");
+  }
 
   if (init_state) {
     hipError_t e = hipSuccess;
@@ -245,6 +258,8 @@ static int create_impl(const sr_params* pin, void* stream, sr_sim** out, bool in
       for (size_t i = 0; i < nsite; ++i)
         if (pin->init_spins[i] != 1 && pin->init_spins[i] != -1) return fail(SR_EINVAL, "init_spins must be +1/-1");
       e = hipMemcpyAsync(L.spins[0], pin->init_spins, nsite, hipMemcpyHostToDevice, s->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(s->init_copy, L.spins[0], nsite, hipMemcpyDeviceToDevice, s->stream);
     }
     if (e != hipSuccess) return fail(SR_EDEVICE, "initial spins failed");
     if (hipMemsetAsync(L.carry[0], 0, (size_t)L.nsub * sizeof(Carry), s->stream) != hipSuccess)
@@ -322,9 +337,15 @@ static int run_one_window(sr_sim* s, int32_t* g_out) {
   for (int it = 0; it < s->p.max_iters; ++it) {
     s->st.it = it;
     HIP_OR_FAIL(s, hipMemsetAsync(L.flags, 0, sizeof(IterFlags), s->stream));
+    HIP_OR_FAIL(s, hipEventRecord(s->ev0, s->stream));
     HIP_OR_FAIL(s, launch_relax(L, s->st, s->stream));
+    HIP_OR_FAIL(s, hipEventRecord(s->ev1, s->stream));
     HIP_OR_FAIL(s, hipMemcpyAsync(s->hflags, L.flags, sizeof(IterFlags), hipMemcpyDeviceToHost, s->stream));
     HIP_OR_FAIL(s, hipStreamSynchronize(s->stream));
+    float ms = 0.f;
+    HIP_OR_FAIL(s, hipEventElapsedTime(&ms, s->ev0, s->ev1));
+    s->relax_ms += ms;
+    s->relax_launches++;
     IterFlags f = *s->hflags;
     s->iterations++;
     s->events += (int64_t)f.events;
@@ -393,6 +414,28 @@ extern "C" int sr_observables(sr_sim* s, sr_obs* o) {
   o->Lx = L.Lx; o->Ly = L.Ly;
   o->window_ticks = s->W;
   o->horizon_ticks = s->H;
+  o->relax_launches = s->relax_launches;
+  o->relax_ms = s->relax_ms;
+  return SR_OK;
+}
+
+extern "C" int sr_reset(sr_sim* s) {
+  if (!s) return SR_EINVAL;
+  Lattice& L = s->L;
+  int64_t nsite = (int64_t)L.Lx * L.Ly;
+  if (s->p.init == SR_INIT_RANDOM) HIP_OR_FAIL(s, launch_init_random(L.spins[0], nsite, s->p.seed, s->stream));
+  else if (s->p.init == SR_INIT_ALL_UP) HIP_OR_FAIL(s, launch_fill(L.spins[0], nsite, 1, s->stream));
+  else if (s->init_copy) HIP_OR_FAIL(s, hipMemcpyAsync(L.spins[0], s->init_copy, (size_t)nsite, hipMemcpyDeviceToDevice, s->stream));
+  else SR_FAIL(s, SR_EINVAL, "no initial spins kept (simulation was loaded from a checkpoint)");
+  HIP_OR_FAIL(s, hipMemsetAsync(L.carry[0], 0, (size_t)L.nsub * sizeof(Carry), s->stream));
+  HIP_OR_FAIL(s, hipStreamSynchronize(s->stream));
+  s->st.t_c = 0; s->st.t_end = 0; s->st.wp = 0; s->st.it = 0;
+  s->windows = s->iterations = s->events = 0;
+  s->last_g = s->last_f = 0;
+  s->relax_launches = 0;
+  s->relax_ms = 0.0;
+  for (auto& v : s->log_tick) v.clear();
+  for (auto& v : s->log_site) v.clear();
   return SR_OK;
 }
 
