@@ -27,6 +27,8 @@ hipError_t launch_init_random(int8_t* s, int64_t n, uint64_t seed, hipStream_t s
 hipError_t launch_fill(int8_t* s, int64_t n, int8_t v, hipStream_t stream);
 hipError_t launch_observables(const int8_t* s, int Lx, int Ly, unsigned long long* out,
                               hipStream_t stream);
+hipError_t launch_batch(const BatchArgs& B, int waves, size_t lds, hipStream_t stream);
+int batch_waves_per_cu(size_t lds);
 }  // namespace sr
 
 using namespace sr;
@@ -41,9 +43,12 @@ struct sr_sim {
   int32_t last_g = 0, last_f = 0;
   unsigned long long* obs = nullptr;   // device scratch for observables
   int8_t* init_copy = nullptr;         // initial spins for sr_reset (SR_INIT_USER)
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev[2 * kMaxBatch] = {};
+  int32_t batch_hint = 8;              // iterations to queue per round trip
   int64_t relax_launches = 0;
   double relax_ms = 0.0;
+  int64_t batch_tasks = 0;
+  double last_batch_ms = 0.0;
   IterFlags* hflags = nullptr;         // pinned host mirror of the flags
   std::vector<std::vector<int64_t>> log_tick, log_site;   // SR_LOG_FULL
   std::string err;
@@ -136,20 +141,17 @@ extern "C" int sr_tune(const sr_params* p, int32_t* bx, int32_t* by, double* win
 
 // ------------------------------------------------------------ buffers
 static void free_hist(sr_sim* s) {
-  for (int q = 0; q < 2; ++q) {
-    if (s->L.hist[q]) (void)hipFree(s->L.hist[q]);
-    s->L.hist[q] = nullptr;
-  }
+  if (s->L.hist) (void)hipFree(s->L.hist);
+  s->L.hist = nullptr;
   if (s->L.wlog) (void)hipFree(s->L.wlog);
   s->L.wlog = nullptr;
 }
 
 static int alloc_hist(sr_sim* s) {
   Lattice& L = s->L;
-  size_t nh = (size_t)L.nsub * kEdges * (size_t)L.hcap;
-  for (int q = 0; q < 2; ++q)
-    if (hipMalloc(&L.hist[q], nh * sizeof(uint64_t)) != hipSuccess)
-      SR_FAIL(s, SR_ENOMEM, "cannot allocate %zu boundary-list entries", nh);
+  size_t nh = 2 * (size_t)L.nsub * kEdges * (size_t)L.hcap;
+  if (hipMalloc(&L.hist, nh * sizeof(uint64_t)) != hipSuccess)
+    SR_FAIL(s, SR_ENOMEM, "cannot allocate %zu boundary-list entries", nh);
   if (hipMalloc(&L.wlog, (size_t)L.nsub * L.wcap * sizeof(uint64_t)) != hipSuccess)
     SR_FAIL(s, SR_ENOMEM, "cannot allocate window logs");
   return SR_OK;
@@ -158,20 +160,22 @@ static int alloc_hist(sr_sim* s) {
 static void free_all(sr_sim* s) {
   Lattice& L = s->L;
   free_hist(s);
-  for (int q = 0; q < 2; ++q) {
-    if (L.spins[q]) (void)hipFree(L.spins[q]);
-    if (L.carry[q]) (void)hipFree(L.carry[q]);
-    if (L.hcnt[q]) (void)hipFree(L.hcnt[q]);
-    L.spins[q] = nullptr; L.carry[q] = nullptr; L.hcnt[q] = nullptr;
-  }
+  if (L.spins) (void)hipFree(L.spins);
+  if (L.carry) (void)hipFree(L.carry);
+  if (L.hcnt) (void)hipFree(L.hcnt);
+  if (L.slot) (void)hipFree(L.slot);
+  if (L.chg) (void)hipFree(L.chg);
+  L.spins = nullptr; L.carry = nullptr; L.hcnt = nullptr; L.slot = nullptr; L.chg = nullptr;
   if (L.wcnt) (void)hipFree(L.wcnt);
   if (L.flags) (void)hipFree(L.flags);
   if (s->obs) (void)hipFree(s->obs);
   if (s->hflags) (void)hipHostFree(s->hflags);
   if (s->init_copy) (void)hipFree(s->init_copy);
-  if (s->ev0) (void)hipEventDestroy(s->ev0);
-  if (s->ev1) (void)hipEventDestroy(s->ev1);
-  s->init_copy = nullptr; s->ev0 = nullptr; s->ev1 = nullptr;
+  for (auto& e : s->ev) {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
+  }
+  s->init_copy = nullptr;
   L.wcnt = nullptr; L.flags = nullptr; s->obs = nullptr; s->hflags = nullptr;
 }
 
@@ -234,35 +238,35 @@ static int create_impl(const sr_params* pin, void* stream, sr_sim** out, bool in
     delete s;
     return code;
   };
-  for (int q = 0; q < 2; ++q) {
-    if (hipMalloc(&L.spins[q], nsite) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate lattice");
-    if (hipMalloc(&L.carry[q], (size_t)L.nsub * sizeof(Carry)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate carry");
-    if (hipMalloc(&L.hcnt[q], (size_t)L.nsub * kEdges * sizeof(uint32_t)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate list counts");
-  }
+  if (hipMalloc(&L.spins, 2 * nsite) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate lattice");
+  if (hipMalloc(&L.carry, 2 * (size_t)L.nsub * sizeof(Carry)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate carry");
+  if (hipMalloc(&L.hcnt, 2 * (size_t)L.nsub * kEdges * sizeof(uint32_t)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate list counts");
+  if (hipMalloc(&L.slot, 2 * (size_t)L.nsub) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate slots");
+  if (hipMalloc(&L.chg, 2 * (size_t)L.nsub) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate change flags");
   if (hipMalloc(&L.wcnt, (size_t)L.nsub * sizeof(uint32_t)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate log counts");
-  if (hipMalloc(&L.flags, sizeof(IterFlags)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate flags");
+  if (hipMalloc(&L.flags, kMaxBatch * sizeof(IterFlags)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate flags");
   if (hipMalloc(&s->obs, 4 * sizeof(unsigned long long)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate scratch");
-  if (hipHostMalloc(&s->hflags, sizeof(IterFlags), hipHostMallocDefault) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate pinned flags");
+  if (hipHostMalloc(&s->hflags, kMaxBatch * sizeof(IterFlags), hipHostMallocDefault) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate pinned flags");
   if (alloc_hist(s) != SR_OK) return fail(SR_ENOMEM, "cannot allocate boundary lists");
-  if (hipEventCreate(&s->ev0) != hipSuccess || hipEventCreate(&s->ev1) != hipSuccess)
-    return fail(SR_EDEVICE, "cannot create events");
+  for (auto& e : s->ev)
+    if (hipEventCreate(&e) != hipSuccess) return fail(SR_EDEVICE, "cannot create events");
   if (p.init == SR_INIT_USER && init_state) {
     if (hipMalloc(&s->init_copy, nsite) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate initial spins");
   }
 
   if (init_state) {
     hipError_t e = hipSuccess;
-    if (p.init == SR_INIT_RANDOM) e = launch_init_random(L.spins[0], (int64_t)nsite, p.seed, s->stream);
-    else if (p.init == SR_INIT_ALL_UP) e = launch_fill(L.spins[0], (int64_t)nsite, 1, s->stream);
+    if (p.init == SR_INIT_RANDOM) e = launch_init_random(spins_at(L, 0), (int64_t)nsite, p.seed, s->stream);
+    else if (p.init == SR_INIT_ALL_UP) e = launch_fill(spins_at(L, 0), (int64_t)nsite, 1, s->stream);
     else {
       for (size_t i = 0; i < nsite; ++i)
         if (pin->init_spins[i] != 1 && pin->init_spins[i] != -1) return fail(SR_EINVAL, "init_spins must be +1/-1");
-      e = hipMemcpyAsync(L.spins[0], pin->init_spins, nsite, hipMemcpyHostToDevice, s->stream);
+      e = hipMemcpyAsync(spins_at(L, 0), pin->init_spins, nsite, hipMemcpyHostToDevice, s->stream);
       if (e == hipSuccess)
-        e = hipMemcpyAsync(s->init_copy, L.spins[0], nsite, hipMemcpyDeviceToDevice, s->stream);
+        e = hipMemcpyAsync(s->init_copy, spins_at(L, 0), nsite, hipMemcpyDeviceToDevice, s->stream);
     }
     if (e != hipSuccess) return fail(SR_EDEVICE, "initial spins failed");
-    if (hipMemsetAsync(L.carry[0], 0, (size_t)L.nsub * sizeof(Carry), s->stream) != hipSuccess)
+    if (hipMemsetAsync(carry_at(L, 0), 0, (size_t)L.nsub * sizeof(Carry), s->stream) != hipSuccess)
       return fail(SR_EDEVICE, "carry init failed");
   }
   if (hipStreamSynchronize(s->stream) != hipSuccess) return fail(SR_EDEVICE, "stream sync failed");
@@ -330,39 +334,59 @@ static int commit(sr_sim* s) {
   return SR_OK;
 }
 
+// One window of the Sec. 4 box.  Iterations are queued K at a time on the
+// stream; an iteration queued after the one that converged (no boundary list
+// changed) or overflowed exits at once, so the host reads the flags of a
+// whole batch in one round trip.
 static int run_one_window(sr_sim* s, int32_t* g_out) {
   Lattice& L = s->L;
   s->st.t_end = std::min(s->st.t_c + s->W, s->H);
   uint32_t fmax = 0;
-  for (int it = 0; it < s->p.max_iters; ++it) {
-    s->st.it = it;
-    HIP_OR_FAIL(s, hipMemsetAsync(L.flags, 0, sizeof(IterFlags), s->stream));
-    HIP_OR_FAIL(s, hipEventRecord(s->ev0, s->stream));
-    HIP_OR_FAIL(s, launch_relax(L, s->st, s->stream));
-    HIP_OR_FAIL(s, hipEventRecord(s->ev1, s->stream));
-    HIP_OR_FAIL(s, hipMemcpyAsync(s->hflags, L.flags, sizeof(IterFlags), hipMemcpyDeviceToHost, s->stream));
+  int it = 0;
+  int K = std::max(2, std::min(kMaxBatch, s->batch_hint));
+  while (it < s->p.max_iters) {
+    int k = std::min(K, s->p.max_iters - it);
+    HIP_OR_FAIL(s, hipMemsetAsync(L.flags, 0, (size_t)k * sizeof(IterFlags), s->stream));
+    for (int i = 0; i < k; ++i) {
+      Step st = s->st;
+      st.it = it + i;
+      st.fi = i;
+      HIP_OR_FAIL(s, hipEventRecord(s->ev[2 * i], s->stream));
+      HIP_OR_FAIL(s, launch_relax(L, st, s->stream));
+      HIP_OR_FAIL(s, hipEventRecord(s->ev[2 * i + 1], s->stream));
+    }
+    HIP_OR_FAIL(s, hipMemcpyAsync(s->hflags, L.flags, (size_t)k * sizeof(IterFlags), hipMemcpyDeviceToHost, s->stream));
     HIP_OR_FAIL(s, hipStreamSynchronize(s->stream));
-    float ms = 0.f;
-    HIP_OR_FAIL(s, hipEventElapsedTime(&ms, s->ev0, s->ev1));
-    s->relax_ms += ms;
-    s->relax_launches++;
-    IterFlags f = *s->hflags;
-    s->iterations++;
-    s->events += (int64_t)f.events;
-    if (f.overflow) {
-      int rc = grow(s, f.overflow);
-      if (rc != SR_OK) return rc;
-      it = -1;                     // re-run the window from its committed state
-      fmax = 0;
-      continue;
+    for (int i = 0; i < k; ++i) {
+      float ms = 0.f;
+      HIP_OR_FAIL(s, hipEventElapsedTime(&ms, s->ev[2 * i], s->ev[2 * i + 1]));
+      s->relax_ms += ms;
     }
-    fmax = std::max(fmax, f.fmax);
-    if (!f.changed) {
-      s->last_g = it + 1;
-      s->last_f = (int32_t)fmax;
-      if (g_out) *g_out = it + 1;
-      return commit(s);
+    s->relax_launches += k;
+    for (int i = 0; i < k; ++i) {
+      const IterFlags& f = s->hflags[i];
+      s->iterations++;
+      s->events += (int64_t)f.events;
+      if (f.overflow) {
+        int rc = grow(s, f.overflow);
+        if (rc != SR_OK) return rc;
+        it = -k;                   // re-run the window from its committed state
+        fmax = 0;
+        break;
+      }
+      fmax = std::max(fmax, f.fmax);
+      if (!f.changed) {
+        int g = it + i + 1;
+        s->last_g = g;
+        s->last_f = (int32_t)fmax;
+        if (g_out) *g_out = g;
+        // queue about as many iterations as the last window needed
+        s->batch_hint = std::max(2, std::min(kMaxBatch, g + 1));
+        return commit(s);
+      }
     }
+    it += k;
+    K = std::max(2, K / 2);
   }
   SR_FAIL(s, SR_ENOCONV, "window [%lld, %lld) did not converge in %d iterations",
           (long long)s->st.t_c, (long long)s->st.t_end, s->p.max_iters);
@@ -393,10 +417,10 @@ extern "C" int sr_observables(sr_sim* s, sr_obs* o) {
   Lattice& L = s->L;
   unsigned long long h[2];
   HIP_OR_FAIL(s, hipMemsetAsync(s->obs, 0, 2 * sizeof(unsigned long long), s->stream));
-  HIP_OR_FAIL(s, launch_observables(L.spins[s->st.wp], L.Lx, L.Ly, s->obs, s->stream));
+  HIP_OR_FAIL(s, launch_observables(spins_at(L, s->st.wp), L.Lx, L.Ly, s->obs, s->stream));
   HIP_OR_FAIL(s, hipMemcpyAsync(h, s->obs, sizeof(h), hipMemcpyDeviceToHost, s->stream));
   std::vector<Carry> c(L.nsub);
-  HIP_OR_FAIL(s, hipMemcpyAsync(c.data(), L.carry[s->st.wp], c.size() * sizeof(Carry), hipMemcpyDeviceToHost, s->stream));
+  HIP_OR_FAIL(s, hipMemcpyAsync(c.data(), carry_at(L, s->st.wp), c.size() * sizeof(Carry), hipMemcpyDeviceToHost, s->stream));
   HIP_OR_FAIL(s, hipStreamSynchronize(s->stream));
   std::memset(o, 0, sizeof(*o));
   o->tick = s->st.t_c;
@@ -423,11 +447,11 @@ extern "C" int sr_reset(sr_sim* s) {
   if (!s) return SR_EINVAL;
   Lattice& L = s->L;
   int64_t nsite = (int64_t)L.Lx * L.Ly;
-  if (s->p.init == SR_INIT_RANDOM) HIP_OR_FAIL(s, launch_init_random(L.spins[0], nsite, s->p.seed, s->stream));
-  else if (s->p.init == SR_INIT_ALL_UP) HIP_OR_FAIL(s, launch_fill(L.spins[0], nsite, 1, s->stream));
-  else if (s->init_copy) HIP_OR_FAIL(s, hipMemcpyAsync(L.spins[0], s->init_copy, (size_t)nsite, hipMemcpyDeviceToDevice, s->stream));
+  if (s->p.init == SR_INIT_RANDOM) HIP_OR_FAIL(s, launch_init_random(spins_at(L, 0), nsite, s->p.seed, s->stream));
+  else if (s->p.init == SR_INIT_ALL_UP) HIP_OR_FAIL(s, launch_fill(spins_at(L, 0), nsite, 1, s->stream));
+  else if (s->init_copy) HIP_OR_FAIL(s, hipMemcpyAsync(spins_at(L, 0), s->init_copy, (size_t)nsite, hipMemcpyDeviceToDevice, s->stream));
   else SR_FAIL(s, SR_EINVAL, "no initial spins kept (simulation was loaded from a checkpoint)");
-  HIP_OR_FAIL(s, hipMemsetAsync(L.carry[0], 0, (size_t)L.nsub * sizeof(Carry), s->stream));
+  HIP_OR_FAIL(s, hipMemsetAsync(carry_at(L, 0), 0, (size_t)L.nsub * sizeof(Carry), s->stream));
   HIP_OR_FAIL(s, hipStreamSynchronize(s->stream));
   s->st.t_c = 0; s->st.t_end = 0; s->st.wp = 0; s->st.it = 0;
   s->windows = s->iterations = s->events = 0;
@@ -441,7 +465,7 @@ extern "C" int sr_reset(sr_sim* s) {
 
 extern "C" int sr_get_spins(sr_sim* s, int8_t* out) {
   if (!s || !out) return SR_EINVAL;
-  HIP_OR_FAIL(s, hipMemcpyAsync(out, s->L.spins[s->st.wp], (size_t)s->L.Lx * s->L.Ly, hipMemcpyDeviceToHost, s->stream));
+  HIP_OR_FAIL(s, hipMemcpyAsync(out, spins_at(s->L, s->st.wp), (size_t)s->L.Lx * s->L.Ly, hipMemcpyDeviceToHost, s->stream));
   HIP_OR_FAIL(s, hipStreamSynchronize(s->stream));
   return SR_OK;
 }
@@ -462,7 +486,7 @@ extern "C" int sr_get_log(sr_sim* s, int32_t d, int64_t* ticks, int64_t* sites, 
 
 static int fetch_carry(sr_sim* s, std::vector<Carry>& c) {
   c.resize(s->L.nsub);
-  HIP_OR_FAIL(s, hipMemcpyAsync(c.data(), s->L.carry[s->st.wp], c.size() * sizeof(Carry), hipMemcpyDeviceToHost, s->stream));
+  HIP_OR_FAIL(s, hipMemcpyAsync(c.data(), carry_at(s->L, s->st.wp), c.size() * sizeof(Carry), hipMemcpyDeviceToHost, s->stream));
   HIP_OR_FAIL(s, hipStreamSynchronize(s->stream));
   return SR_OK;
 }
@@ -523,8 +547,8 @@ extern "C" int sr_save(sr_sim* s, void* blob, size_t cap, size_t* n) {
   h.last_g = s->last_g; h.last_f = s->last_f; h.nsub = s->L.nsub;
   char* b = (char*)blob;
   std::memcpy(b, &h, sizeof(h));
-  HIP_OR_FAIL(s, hipMemcpyAsync(b + sizeof(h), s->L.spins[s->st.wp], nsite, hipMemcpyDeviceToHost, s->stream));
-  HIP_OR_FAIL(s, hipMemcpyAsync(b + sizeof(h) + nsite, s->L.carry[s->st.wp], (size_t)s->L.nsub * sizeof(Carry), hipMemcpyDeviceToHost, s->stream));
+  HIP_OR_FAIL(s, hipMemcpyAsync(b + sizeof(h), spins_at(s->L, s->st.wp), nsite, hipMemcpyDeviceToHost, s->stream));
+  HIP_OR_FAIL(s, hipMemcpyAsync(b + sizeof(h) + nsite, carry_at(s->L, s->st.wp), (size_t)s->L.nsub * sizeof(Carry), hipMemcpyDeviceToHost, s->stream));
   HIP_OR_FAIL(s, hipStreamSynchronize(s->stream));
   return SR_OK;
 }
@@ -541,8 +565,8 @@ extern "C" int sr_load(const void* blob, size_t n, void* stream, sr_sim** out) {
   sr_sim* s = *out;
   if (s->L.nsub != h.nsub) { sr_destroy(s); *out = nullptr; SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "checkpoint does not match its parameters"); }
   const char* b = (const char*)blob;
-  HIP_OR_FAIL(s, hipMemcpyAsync(s->L.spins[0], b + sizeof(h), nsite, hipMemcpyHostToDevice, s->stream));
-  HIP_OR_FAIL(s, hipMemcpyAsync(s->L.carry[0], b + sizeof(h) + nsite, (size_t)h.nsub * sizeof(Carry), hipMemcpyHostToDevice, s->stream));
+  HIP_OR_FAIL(s, hipMemcpyAsync(spins_at(s->L, 0), b + sizeof(h), nsite, hipMemcpyHostToDevice, s->stream));
+  HIP_OR_FAIL(s, hipMemcpyAsync(carry_at(s->L, 0), b + sizeof(h) + nsite, (size_t)h.nsub * sizeof(Carry), hipMemcpyHostToDevice, s->stream));
   HIP_OR_FAIL(s, hipStreamSynchronize(s->stream));
   s->st.t_c = h.t_c; s->st.wp = 0;
   s->windows = h.windows; s->iterations = h.iterations; s->events = h.events;
@@ -550,12 +574,132 @@ extern "C" int sr_load(const void* blob, size_t n, void* stream, sr_sim** out) {
   return SR_OK;
 }
 
-// ------------------------------------------------------------ batch (stub until built)
-extern "C" int sr_batch_run(sr_sim* const* sims, int32_t n, void* stream) {
-  (void)stream;
-  for (int32_t i = 0; i < n; ++i) {
-    int rc = sr_run_window(sims[i], -1, nullptr, nullptr);
-    if (rc != SR_OK) return rc;
+// ------------------------------------------------------------ batched form
+// One persistent launch runs every listed simulation to its horizon: resident
+// waves take (lattice, subdomain) tasks from a device queue; the last task of
+// a lattice's iteration decides convergence and enqueues the next iteration
+// (only subdomains whose inputs changed) or the next window.  Lattices whose
+// buffers overflowed are finished afterwards by the plain path with larger
+// buffers, from their last committed window.
+extern "C" int sr_batch_run(sr_sim* const* sims, int32_t n, void* stream_) {
+  if (!sims || n <= 0) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "sr_batch_run needs simulations");
+  if (n > 4096) SR_FAIL(sims[0], SR_EINVAL, "at most 4096 lattices per batch");
+  hipStream_t stream = (hipStream_t)stream_;
+  std::vector<int> idx;
+  size_t lds = 16;
+  uint64_t total = 0;
+  for (int i = 0; i < n; ++i) {
+    sr_sim* s = sims[i];
+    if (!s) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "null simulation in batch");
+    if (s->p.log_mode != SR_LOG_DIGEST) SR_FAIL(s, SR_EINVAL, "batched runs keep digests only (SR_LOG_DIGEST)");
+    if (s->L.nsub >= (1 << 20)) SR_FAIL(s, SR_EINVAL, "too many subdomains for the batch queue");
+    if (s->st.t_c >= s->H) continue;
+    idx.push_back(i);
+    lds = std::max(lds, (size_t)((s->L.bx + 2) * (s->L.by + 2) + 15) & ~(size_t)15);
+    total += (uint64_t)s->L.nsub;
   }
-  return SR_OK;
+  if (idx.empty()) return SR_OK;
+  sr_sim* s0 = sims[idx[0]];
+  int m = (int)idx.size();
+  int dev = 0, ncu = 0;
+  HIP_OR_FAIL(s0, hipGetDevice(&dev));
+  HIP_OR_FAIL(s0, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  int per_cu = batch_waves_per_cu(lds);
+  if (per_cu <= 0) SR_FAIL(s0, SR_EDEVICE, "cannot size the persistent grid");
+  int waves = per_cu * ncu;
+  uint64_t qn = 1;
+  while (qn < total + (uint64_t)waves + 64) qn <<= 1;
+
+  std::vector<Lattice> lat(m);
+  std::vector<LatRun> run(m);
+  std::vector<unsigned long long> q(qn, 0ull);
+  uint64_t t = 0;
+  for (int k = 0; k < m; ++k) {
+    sr_sim* s = sims[idx[k]];
+    lat[k] = s->L;
+    LatRun& r = run[k];
+    std::memset(&r, 0, sizeof(r));
+    r.st = s->st;
+    r.st.it = 0; r.st.fi = 0;
+    r.st.t_end = std::min(s->st.t_c + s->W, s->H);
+    r.H = s->H; r.W = s->W;
+    r.remaining = s->L.nsub;
+    r.max_iters = s->p.max_iters;
+    r.status = kRunning;
+    r.tasks = s->L.nsub;
+    for (int d = 0; d < s->L.nsub; ++d, ++t)
+      q[t] = ((unsigned long long)(t + 1) << 32) | ((unsigned long long)k << 20) | (unsigned)d;
+  }
+  Lattice* dlat = nullptr;
+  LatRun* drun = nullptr;
+  unsigned long long* dq = nullptr;
+  BatchCounters* dctr = nullptr;
+  auto release = [&]() {
+    if (dlat) (void)hipFree(dlat);
+    if (drun) (void)hipFree(drun);
+    if (dq) (void)hipFree(dq);
+    if (dctr) (void)hipFree(dctr);
+  };
+  if (hipMalloc(&dlat, m * sizeof(Lattice)) != hipSuccess || hipMalloc(&drun, m * sizeof(LatRun)) != hipSuccess ||
+      hipMalloc(&dq, qn * sizeof(unsigned long long)) != hipSuccess || hipMalloc(&dctr, sizeof(BatchCounters)) != hipSuccess) {
+    release();
+    SR_FAIL(s0, SR_ENOMEM, "cannot allocate the batch queue");
+  }
+  BatchCounters ctr;
+  std::memset(&ctr, 0, sizeof(ctr));
+  ctr.head = 0; ctr.tail = total; ctr.done = 0;
+  BatchArgs args;
+  args.ctr = dctr; args.q = dq; args.lat = dlat; args.run = drun;
+  args.nlat = (uint32_t)m; args.qmask = (uint32_t)(qn - 1);
+  hipEvent_t e0 = s0->ev[0], e1 = s0->ev[1];
+  int rc = SR_OK;
+  if (hipMemcpyAsync(dlat, lat.data(), m * sizeof(Lattice), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(drun, run.data(), m * sizeof(LatRun), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(dq, q.data(), qn * sizeof(unsigned long long), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(dctr, &ctr, sizeof(ctr), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipEventRecord(e0, stream) != hipSuccess || launch_batch(args, waves, lds, stream) != hipSuccess ||
+      hipEventRecord(e1, stream) != hipSuccess ||
+      hipMemcpyAsync(run.data(), drun, m * sizeof(LatRun), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess) {
+    release();
+    SR_FAIL(s0, SR_EDEVICE, "persistent batch kernel failed: %s", hipGetErrorString(hipGetLastError()));
+  }
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  release();
+  std::string first_err;
+  for (int k = 0; k < m; ++k) {
+    sr_sim* s = sims[idx[k]];
+    const LatRun& r = run[k];
+    s->st.t_c = r.st.t_c;
+    s->st.wp = r.st.wp;
+    s->windows += r.windows;
+    s->iterations += r.iterations;
+    s->events += r.events;
+    if (r.windows) { s->last_g = r.last_g; s->last_f = r.last_f; }
+    s->relax_launches += 1;
+    s->relax_ms += ms;
+    s->batch_tasks += r.tasks;
+    int one = SR_OK;
+    if (r.status == kOverflow) {
+      // grow and finish alone from the last committed window
+      one = grow(s, 3u);
+      if (one == SR_OK) one = sr_run_window(s, -1, nullptr, nullptr);
+    } else if (r.status == kNoConv) {
+      one = SR_ENOCONV;
+      s->err = "window did not converge within max_iters (batched run)";
+    } else if (r.status != kDone) {
+      one = SR_EDEVICE;
+      s->err = "batched run ended early (status " + std::to_string(r.status) + ")";
+    }
+    if (one != SR_OK && rc == SR_OK) {
+      rc = one;
+      char b[256];
+      std::snprintf(b, sizeof(b), "lattice %d of the batch (status %d): %s", idx[k], r.status, s->err.c_str());
+      first_err = b;
+    }
+  }
+  if (rc != SR_OK) for (int k = 0; k < m; ++k) sims[idx[k]]->err = first_err;
+  s0->last_batch_ms = ms;
+  return rc;
 }

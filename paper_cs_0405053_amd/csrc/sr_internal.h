@@ -44,20 +44,79 @@ struct Lattice {
   uint32_t seed_lo, seed_hi;
   int32_t hcap;           // entries per boundary list
   int32_t wcap;           // entries per subdomain window log
-  int8_t* spins[2];       // committed lattice, indexed by window parity
-  Carry* carry[2];        // indexed by window parity
-  uint64_t* hist[2];      // [nsub][4][hcap], indexed by iteration parity
-  uint32_t* hcnt[2];      // [nsub][4]
+  // Double buffers are single allocations; buffer q starts at base + q * stride.
+  int8_t* spins;          // 2 x Lx*Ly: committed lattice, by window parity
+  Carry* carry;           // 2 x nsub: by window parity
+  uint64_t* hist;         // 2 x [nsub][4][hcap]: two list slots per subdomain
+  uint32_t* hcnt;         // 2 x [nsub][4]: list lengths, per slot
+  uint8_t* slot;          // 2 x nsub: slot holding a subdomain's latest lists,
+                          // by iteration parity
+  uint8_t* chg;           // 2 x nsub: lists changed in that iteration, by parity
   uint64_t* wlog;         // [nsub][wcap]: tick << 16 | local site
   uint32_t* wcnt;         // [nsub]
-  IterFlags* flags;
+  IterFlags* flags;       // [kMaxBatch], one per queued iteration
 };
 
-// Where a lattice stands in its window loop (host mirror and device copy).
+constexpr int kMaxBatch = 64;   // iterations queued per host round trip
+
+// Buffer q (0 or 1) of a double buffer.
+template <class LT>
+__host__ __device__ inline int8_t* spins_at(const LT& L, int q) {
+  return L.spins + (int64_t)(q & 1) * ((int64_t)L.Lx * L.Ly);
+}
+template <class LT>
+__host__ __device__ inline Carry* carry_at(const LT& L, int q) { return L.carry + (q & 1) * L.nsub; }
+template <class LT>
+__host__ __device__ inline uint64_t* hist_at(const LT& L, int q) {
+  return L.hist + (int64_t)(q & 1) * ((int64_t)L.nsub * kEdges * L.hcap);
+}
+template <class LT>
+__host__ __device__ inline uint32_t* hcnt_at(const LT& L, int q) {
+  return L.hcnt + (q & 1) * (L.nsub * kEdges);
+}
+template <class LT>
+__host__ __device__ inline uint8_t* slot_at(const LT& L, int q) { return L.slot + (q & 1) * L.nsub; }
+template <class LT>
+__host__ __device__ inline uint8_t* chg_at(const LT& L, int q) { return L.chg + (q & 1) * L.nsub; }
+
+// Where a lattice stands in its window loop.
 struct Step {
   int64_t t_c, t_end;     // window [t_c, t_end)
   int32_t wp;             // window parity: spins[wp], carry[wp] are committed
   int32_t it;             // iteration index within the window
+  int32_t fi;             // this iteration's entry in Lattice::flags
+  int32_t pad;
+};
+
+// Per-lattice state of the persistent batched kernel (device resident).
+struct LatRun {
+  Step st;                 // current window and iteration
+  IterFlags fl;            // flags of the current iteration
+  int64_t H, W;            // horizon and window (ticks)
+  int32_t remaining;       // tasks of the current iteration still running
+  int32_t max_iters;
+  int32_t status;          // kRunning, kDone, kOverflow, kNoConv
+  int32_t last_g, last_f;
+  uint32_t fmax_win;
+  int64_t windows, iterations, events, tasks;
+};
+enum { kRunning = 0, kDone = 1, kOverflow = 2, kNoConv = 3 };
+
+// Device work queue of (lattice, subdomain) tasks.  A slot holds
+// (ticket + 1) << 32 | lattice << 20 | subdomain; a consumer owning ticket p
+// waits until slot p & qmask carries p + 1.
+struct BatchCounters {
+  unsigned long long head;     // next ticket to hand to a consumer
+  unsigned long long tail;     // next ticket to hand to a producer
+  uint32_t done;               // lattices finished
+  uint32_t pad;
+};
+struct BatchArgs {             // read-only for the kernel's lifetime
+  BatchCounters* ctr;
+  unsigned long long* q;
+  const Lattice* lat;
+  LatRun* run;
+  uint32_t nlat, qmask;
 };
 
 }  // namespace sr

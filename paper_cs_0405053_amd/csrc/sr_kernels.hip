@@ -40,6 +40,7 @@ __device__ __forceinline__ uint64_t rdl64(uint64_t v, int l) {
 __device__ __forceinline__ int ctz64(uint64_t m) { return __builtin_ctzll(m); }
 __device__ __forceinline__ int64_t min64(int64_t a, int64_t b) { return a < b ? a : b; }
 
+
 template <int CTRL, int ROWMASK>
 __device__ __forceinline__ uint32_t dpp0(uint32_t x) {
   // lanes whose DPP source is outside the row (or whose row is masked off)
@@ -228,8 +229,9 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
 
 // ------------------------------------------------------------ relaxation
 // One subdomain (this wave) over one window, one iteration.
-__device__ __forceinline__ void relax_subdomain(const Lattice& L, const Step& st, int d,
-                                                int8_t* tile) {
+template <class LT>
+__device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int d,
+                                                int8_t* tile, IterFlags* fl) {
   const int lane = lane_id();
   const int bx = L.bx, by = L.by, sh = L.sshift, S = 1 << sh;
   const int nbx = L.nbx, nby = L.nby;
@@ -238,9 +240,19 @@ __device__ __forceinline__ void relax_subdomain(const Lattice& L, const Step& st
   const int nblk = bx * by;
   const bool wrapx = (nbx == 1), wrapy = (nby == 1);
   const int first = (st.it == 0);
-  const int pin = (st.it + 1) & 1, pout = st.it & 1;
   const int hcap = L.hcap;
-  const int8_t* sp = L.spins[st.wp];
+  const int dn = ((cy + nby - 1) % nby) * nbx + cx;
+  const int ds = ((cy + 1) % nby) * nbx + cx;
+  const int dw = cy * nbx + (cx + nbx - 1) % nbx;
+  const int de = cy * nbx + (cx + 1) % nbx;
+  uint8_t* slot_now = slot_at(L, st.it & 1);
+  const uint8_t* slot_prev = slot_at(L, (st.it + 1) & 1);
+  uint8_t* chg_now = chg_at(L, st.it & 1);
+  const uint8_t* chg_prev = chg_at(L, (st.it + 1) & 1);
+  const int sprev = first ? 0 : slot_prev[d];
+  (void)chg_prev;
+  const int sout = first ? 0 : 1 - sprev;
+  const int8_t* sp = spins_at(L, st.wp);
   const int tw = bx + 2;
 
   // committed block + one-site halo -> LDS (internal wrap falls out of the
@@ -288,7 +300,7 @@ __device__ __forceinline__ void relax_subdomain(const Lattice& L, const Step& st
     if (lane == k) rate = L.rate[k];
 
   // carry at committed time, presimulated randoms
-  const Carry* cin = &L.carry[st.wp][d];
+  const Carry* cin = &carry_at(L, st.wp)[d];
   uint64_t j = cin->j, acc = cin->acc;
   int64_t anchor = cin->anchor;
   const uint32_t k0 = L.seed_lo, k1 = L.seed_hi;
@@ -300,28 +312,30 @@ __device__ __forceinline__ void relax_subdomain(const Lattice& L, const Step& st
   uint64_t lam = rdl64(C, kClasses - 1);
   int64_t next = next_tick(anchor, E, acc, lam);
 
-  // neighbour histories of the previous iteration (break points);
-  // the first iteration assumes none (canonical assumption)
-  const int dn = ((cy + nby - 1) % nby) * nbx + cx;
-  const int ds = ((cy + 1) % nby) * nbx + cx;
-  const int dw = cy * nbx + (cx + nbx - 1) % nbx;
-  const int de = cy * nbx + (cx + 1) % nbx;
-  const uint64_t* hin = L.hist[pin];
-  const uint32_t* cin_n = L.hcnt[pin];
+  // neighbour histories of the previous iteration (break points), each in
+  // the slot its owner last wrote; the first iteration assumes none
+  // (canonical assumption)
   auto clampn = [&](uint32_t n) { return (int)(n < (uint32_t)hcap ? n : (uint32_t)hcap); };
+  auto in_list = [&](ListIn& li, int e, int edge, bool none) {
+    int q = none ? 0 : slot_prev[e];
+    list_open(li, hist_at(L, q) + ((size_t)e * kEdges + edge) * hcap,
+              none ? 0 : clampn(hcnt_at(L, q)[e * kEdges + edge]), lane);
+  };
   ListIn inN, inS, inW, inE;
-  list_open(inN, hin + ((size_t)dn * kEdges + kS) * hcap, (first || wrapy) ? 0 : clampn(cin_n[dn * kEdges + kS]), lane);
-  list_open(inS, hin + ((size_t)ds * kEdges + kN) * hcap, (first || wrapy) ? 0 : clampn(cin_n[ds * kEdges + kN]), lane);
-  list_open(inW, hin + ((size_t)dw * kEdges + kE) * hcap, (first || wrapx) ? 0 : clampn(cin_n[dw * kEdges + kE]), lane);
-  list_open(inE, hin + ((size_t)de * kEdges + kW) * hcap, (first || wrapx) ? 0 : clampn(cin_n[de * kEdges + kW]), lane);
+  in_list(inN, dn, kS, first || wrapy);
+  in_list(inS, ds, kN, first || wrapy);
+  in_list(inW, dw, kE, first || wrapx);
+  in_list(inE, de, kW, first || wrapx);
 
-  // own lists of this iteration, compared with those of the previous one
-  uint64_t* hout = L.hist[pout];
+  // own lists of this iteration (into the other slot), compared with the
+  // ones of the previous iteration
+  auto own_list = [&](ListOut& lo, int edge) {
+    out_open(lo, hist_at(L, sout) + ((size_t)d * kEdges + edge) * hcap, hcap,
+             hist_at(L, sprev) + ((size_t)d * kEdges + edge) * hcap,
+             first ? 0 : clampn(hcnt_at(L, sprev)[d * kEdges + edge]), lane);
+  };
   ListOut oN, oS, oW, oE;
-  out_open(oN, hout + ((size_t)d * kEdges + kN) * hcap, hcap, hin + ((size_t)d * kEdges + kN) * hcap, first ? 0 : clampn(cin_n[d * kEdges + kN]), lane);
-  out_open(oS, hout + ((size_t)d * kEdges + kS) * hcap, hcap, hin + ((size_t)d * kEdges + kS) * hcap, first ? 0 : clampn(cin_n[d * kEdges + kS]), lane);
-  out_open(oW, hout + ((size_t)d * kEdges + kW) * hcap, hcap, hin + ((size_t)d * kEdges + kW) * hcap, first ? 0 : clampn(cin_n[d * kEdges + kW]), lane);
-  out_open(oE, hout + ((size_t)d * kEdges + kE) * hcap, hcap, hin + ((size_t)d * kEdges + kE) * hcap, first ? 0 : clampn(cin_n[d * kEdges + kE]), lane);
+  own_list(oN, kN); own_list(oS, kS); own_list(oW, kW); own_list(oE, kE);
 
   // window event log (tick << 16 | local site), buffered 64 at a time
   uint64_t* wl = L.wlog + (size_t)d * L.wcap;
@@ -451,7 +465,7 @@ __device__ __forceinline__ void relax_subdomain(const Lattice& L, const Step& st
   out_close(oN, lane); out_close(oS, lane); out_close(oW, lane); out_close(oE, lane);
 
   // end-of-window block -> working lattice (the other window parity)
-  int8_t* so = L.spins[st.wp ^ 1];
+  int8_t* so = spins_at(L, st.wp ^ 1);
   for (int i = 0; i < S; ++i) {
     int v = base + i;
     if (v < nblk) {
@@ -461,31 +475,220 @@ __device__ __forceinline__ void relax_subdomain(const Lattice& L, const Step& st
     }
   }
   uint64_t dtot = wave_sum64(dsum);
-  uint32_t* cnt_out = L.hcnt[pout] + d * kEdges;
+  uint32_t* cnt_out = hcnt_at(L, sout) + d * kEdges;
   if (lane == 0) {
     cnt_out[kN] = (uint32_t)oN.n; cnt_out[kS] = (uint32_t)oS.n;
     cnt_out[kW] = (uint32_t)oW.n; cnt_out[kE] = (uint32_t)oE.n;
-    Carry* co = &L.carry[st.wp ^ 1][d];
+    Carry* co = &carry_at(L, st.wp ^ 1)[d];
     co->j = j; co->anchor = anchor; co->acc = acc;
     co->digest = cin->digest + dtot;
     co->flips = cin->flips + nev;
     co->wflips = nev;
     L.wcnt[d] = (uint32_t)nev;
     bool changed = oN.diff || oS.diff || oW.diff || oE.diff;
+    slot_now[d] = (uint8_t)sout;
+    chg_now[d] = changed ? 1 : 0;
     uint32_t ovf = ((oN.n > hcap || oS.n > hcap || oW.n > hcap || oE.n > hcap) ? 1u : 0u) |
                    ((nev > wcap || runaway) ? 2u : 0u);
-    if (changed) atomicOr(&L.flags->changed, 1u);
-    if (ovf) atomicOr(&L.flags->overflow, ovf);
-    atomicMax(&L.flags->fmax, (uint32_t)nbound);
-    atomicAdd(&L.flags->events, (unsigned long long)nev);
+    if (changed) atomicOr(&fl->changed, 1u);
+    if (ovf) atomicOr(&fl->overflow, ovf);
+    atomicMax(&fl->fmax, (uint32_t)nbound);
+    atomicAdd(&fl->events, (unsigned long long)nev);
   }
+}
+
+// Does subdomain d have to run in iteration st.it (> 0)?  Only if one of its
+// external neighbours' lists changed in the previous iteration: the same
+// inputs give the same outputs.
+template <class LT>
+__device__ __forceinline__ bool inputs_changed(const LT& L, int it, int d) {
+  const int nbx = L.nbx, nby = L.nby;
+  const int cx = d % nbx, cy = d / nbx;
+  const uint8_t* c = chg_at(L, (it + 1) & 1);
+  bool need = false;
+  if (nby > 1) need |= (c[((cy + nby - 1) % nby) * nbx + cx] | c[((cy + 1) % nby) * nbx + cx]) != 0;
+  if (nbx > 1) need |= (c[cy * nbx + (cx + nbx - 1) % nbx] | c[cy * nbx + (cx + 1) % nbx]) != 0;
+  return need;
 }
 
 __global__ __launch_bounds__(64) void relax_kernel(Lattice L, Step st) {
   extern __shared__ int8_t tile[];
   const int d = blockIdx.x;
   if (d >= L.nsub) return;
-  relax_subdomain(L, st, d, tile);
+  if (st.fi > 0) {
+    // queued behind an iteration that already converged (or overflowed):
+    // nothing to do
+    const IterFlags* fp = L.flags + st.fi - 1;
+    if (fp->changed == 0 || fp->overflow != 0) return;
+  }
+  if (st.it > 0 && !inputs_changed(L, st.it, d)) {
+    // keep the previous outputs (lists, window state, log): skip the run
+    if (lane_id() == 0) {
+      slot_at(L, st.it & 1)[d] = slot_at(L, (st.it + 1) & 1)[d];
+      chg_at(L, st.it & 1)[d] = 0;
+    }
+    return;
+  }
+  relax_subdomain(L, st, d, tile, L.flags + st.fi);
+}
+
+// ------------------------------------------------------------ batched form
+// Per-lattice descriptors are read through the constant address space: they
+// do not change while the kernel runs, so the compiler may keep their fields
+// in scalar registers or reload them instead of pinning ~100 values.
+typedef const __attribute__((address_space(4))) Lattice CLattice;
+
+// Mutable per-lattice state read at a wave-uniform address, field by field
+// through readfirstlane so that it lives in scalar registers.
+__device__ __forceinline__ int32_t u32s(const int32_t& x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint32_t u32s(const uint32_t& x) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+}
+__device__ __forceinline__ int64_t u64s(const int64_t& x) {
+  uint64_t v = (uint64_t)x;
+  return (int64_t)(((uint64_t)u32s((uint32_t)(v >> 32)) << 32) | u32s((uint32_t)v));
+}
+__device__ __forceinline__ Step load_step(const Step* p) {
+  Step st;
+  st.t_c = u64s(p->t_c); st.t_end = u64s(p->t_end);
+  st.wp = u32s(p->wp); st.it = u32s(p->it); st.fi = u32s(p->fi); st.pad = 0;
+  return st;
+}
+__device__ __forceinline__ IterFlags load_flags(const IterFlags* p) {
+  IterFlags f;
+  f.changed = u32s(p->changed); f.overflow = u32s(p->overflow); f.fmax = u32s(p->fmax);
+  f.pad0 = 0;
+  f.events = (unsigned long long)u64s(reinterpret_cast<const int64_t&>(p->events));
+  return f;
+}
+
+// Wave-cooperative enqueue of the subdomains of lattice `lat` that run in
+// iteration `it` (all of them when it == 0); the others keep their lists.
+// Sets run.remaining before publishing anything.
+__device__ void enqueue_iteration(const BatchArgs& B, int lat, LatRun* run, CLattice& L, int it,
+                                  int lane) {
+  const int nsub = L.nsub;
+  uint32_t count = 0;
+  for (int b = 0; b < nsub; b += 64) {
+    int d = b + lane;
+    bool need = d < nsub && (it == 0 || inputs_changed(L, it, d));
+    count += (uint32_t)__popcll(ballot(need));
+    if (d < nsub && !need) {
+      slot_at(L, it & 1)[d] = slot_at(L, (it + 1) & 1)[d];
+      chg_at(L, it & 1)[d] = 0;
+    }
+  }
+  if (lane == 0) {
+    run->remaining = (int32_t)count;
+    run->tasks += count;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  for (int b = 0; b < nsub; b += 64) {
+    int d = b + lane;
+    bool need = d < nsub && (it == 0 || inputs_changed(L, it, d));
+    uint64_t m = ballot(need);
+    if (!m) continue;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(&B.ctr->tail, (unsigned long long)__popcll(m));
+    base = ((uint64_t)rdl((uint32_t)(base >> 32), 0) << 32) | rdl((uint32_t)base, 0);
+    if (need) {
+      uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+      unsigned long long t = base + below;
+      unsigned long long v = ((t + 1) << 32) | ((unsigned long long)lat << 20) | (unsigned)d;
+      __hip_atomic_store(&B.q[t & B.qmask], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// The last task of an iteration of lattice `lat`: compare step (c) of the
+// Sec. 4 box for the whole lattice, then the next iteration, the next
+// window (committed time advances), or completion.
+__device__ void decide(const BatchArgs& B, int lat, int lane) {
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  LatRun* run = &B.run[lat];
+  CLattice& L = ((CLattice*)B.lat)[lat];
+  const IterFlags f = load_flags(&run->fl);
+  Step st = load_step(&run->st);
+  bool finish = false;
+  if (lane == 0) {
+    run->iterations += 1;
+    run->events += (int64_t)f.events;
+    run->fmax_win = max(run->fmax_win, f.fmax);
+  }
+  int next_it = -1;
+  if (f.overflow) {
+    if (lane == 0) run->status = kOverflow;
+    finish = true;
+  } else if (f.changed) {
+    if (st.it + 1 >= run->max_iters) {
+      if (lane == 0) run->status = kNoConv;
+      finish = true;
+    } else {
+      next_it = st.it + 1;
+    }
+  } else {
+    // converged: the working outputs become committed (parity flip)
+    st.wp ^= 1;
+    st.t_c = st.t_end;
+    if (lane == 0) {
+      run->windows += 1;
+      run->last_g = st.it + 1;
+      run->last_f = (int32_t)run->fmax_win;
+      run->fmax_win = 0;
+    }
+    if (st.t_c >= run->H) {
+      if (lane == 0) { run->status = kDone; run->st = st; }
+      finish = true;
+    } else {
+      st.t_end = min64(st.t_c + run->W, run->H);
+      next_it = 0;
+    }
+  }
+  if (finish) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (lane == 0) atomicAdd(&B.ctr->done, 1u);
+    return;
+  }
+  st.it = next_it;
+  st.fi = 0;
+  if (lane == 0) {
+    run->st = st;
+    run->fl.changed = 0; run->fl.overflow = 0; run->fl.fmax = 0; run->fl.events = 0;
+  }
+  enqueue_iteration(B, lat, run, L, next_it, lane);
+}
+
+__global__ __launch_bounds__(64) void batch_kernel(BatchArgs B) {
+  extern __shared__ int8_t tile[];
+  const int lane = lane_id();
+  CLattice* lats = (CLattice*)B.lat;
+  for (;;) {
+    unsigned long long t = 0;
+    if (lane == 0) t = atomicAdd(&B.ctr->head, 1ull);
+    t = ((uint64_t)rdl((uint32_t)(t >> 32), 0) << 32) | rdl((uint32_t)t, 0);
+    const uint32_t want = (uint32_t)(t + 1);
+    unsigned long long v;
+    for (;;) {
+      v = __hip_atomic_load(&B.q[t & B.qmask], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if ((uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32)) == want) break;
+      if (__hip_atomic_load(&B.ctr->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= B.nlat) return;
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    // the task is wave-uniform: keep it (and all that derives from it) scalar
+    const uint32_t pay = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const int lat = (int)((pay >> 20) & 0xFFF);
+    const int d = (int)(pay & 0xFFFFF);
+    LatRun* run = &B.run[lat];
+    const Step st = load_step(&run->st);
+    relax_subdomain(lats[lat], st, d, tile, &run->fl);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    int last = 0;
+    if (lane == 0) last = (atomicSub(&run->remaining, 1) == 1);
+    last = (int)rdl((uint32_t)last, 0);
+    if (last) decide(B, lat, lane);
+  }
 }
 
 // ------------------------------------------------------------ init / observables
@@ -534,6 +737,17 @@ hipError_t launch_relax(const Lattice& L, const Step& st, hipStream_t stream) {
   lds = (lds + 15) & ~(size_t)15;
   hipLaunchKernelGGL(relax_kernel, dim3(L.nsub), dim3(64), lds, stream, L, st);
   return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchArgs& B, int waves, size_t lds, hipStream_t stream) {
+  hipLaunchKernelGGL(batch_kernel, dim3(waves), dim3(64), lds, stream, B);
+  return hipGetLastError();
+}
+
+int batch_waves_per_cu(size_t lds) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel, 64, lds) != hipSuccess) return 0;
+  return n;
 }
 
 hipError_t launch_init_random(int8_t* s, int64_t n, uint64_t seed, hipStream_t stream) {

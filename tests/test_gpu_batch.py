@@ -1,0 +1,134 @@
+"""Persistent batched form (one launch, device work queue) against the plain
+form and the oracle: bit-identical committed state for every lattice, the same
+iteration counts, and the same result alone as inside a mix."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _sr():
+    import paper_cs_0405053_amd as sr
+    return sr
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def mix(n=12, horizon=3.0, seed=7):
+    rng = np.random.default_rng(seed)
+    ps = []
+    for i in range(n):
+        L = int(16 * rng.integers(2, 9))
+        b = int([4, 8, 16][rng.integers(0, 3)])
+        b = min(b, L)
+        ps.append(W.params(L, L, b, b, T=float(rng.uniform(1.0, 3.5)), h=float(rng.uniform(-0.2, 0.2)),
+                           window=float([0.25, 0.5, 1.0][rng.integers(0, 3)]),
+                           horizon=float(horizon * rng.uniform(0.5, 1.0)), seed=100 + i,
+                           log_mode="digest", rule=["metropolis", "glauber"][i % 2]))
+    return ps
+
+
+def state(s):
+    o = s.observables()
+    return (s.spins().copy(), s.digests()[0].copy(), s.digests()[1].copy(), s.carry().copy(),
+            o["tick"], o["windows"], o["iterations"], o["flips"])
+
+
+def same(a, b):
+    return (np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+            and np.array_equal(a[3], b[3]) and a[4:] == b[4:])
+
+
+def test_batched_equals_plain_and_oracle():
+    sr = _sr()
+    ps = mix()
+    say("plain")
+    plain = []
+    for p in ps:
+        s = sr.Sim(p)
+        s.run()
+        plain.append(state(s))
+        s.close()
+    say("batched")
+    sims = [sr.Sim(p) for p in ps]
+    sr.batch_run(sims)
+    for i, (p, s) in enumerate(zip(ps, sims)):
+        got = state(s)
+        assert same(got, plain[i]), f"lattice {i} differs from its plain run"
+    for i in (0, 3, 7):
+        ref = oracle.des(ps[i], log=False)
+        assert np.array_equal(sims[i].spins(), ref["spins"])
+        assert np.array_equal(sims[i].digests()[0], ref["sub_digest"])
+    for s in sims:
+        s.close()
+
+
+def test_alone_equals_in_mix():
+    sr = _sr()
+    ps = mix(n=8, seed=11)
+    target = ps[5]
+    alone = sr.Sim(target)
+    sr.batch_run([alone])
+    a = state(alone)
+    sims = [sr.Sim(p) for p in ps]
+    sr.batch_run(sims)
+    assert same(state(sims[5]), a)
+
+
+def test_batch_resumes_partial_runs_and_reset():
+    sr = _sr()
+    ps = mix(n=6, seed=3)
+    sims = [sr.Sim(p) for p in ps]
+    for s in sims[:3]:
+        s.run(2)                 # some lattices already advanced
+    sr.batch_run(sims)
+    ref = [sr.Sim(p) for p in ps]
+    for s in ref:
+        s.run()
+    for a, b in zip(sims, ref):
+        assert same(state(a), state(b))
+    for s in sims:
+        s.reset()
+    sr.batch_run(sims)
+    for a, b in zip(sims, ref):
+        assert same(state(a)[:5], state(b)[:5])
+
+
+def test_batch_overflow_falls_back_and_matches():
+    sr = _sr()
+    p = W.params(32, 32, 16, 16, T=3.0, h=0.0, window=2.0, horizon=4.0, seed=9, log_mode="digest")
+    ref = sr.Sim(p)
+    ref.run()
+    tiny = sr.Sim(dict(p, hist_cap=1, wlog_cap=2))
+    other = sr.Sim(W.params(32, 32, 8, 8, T=2.0, h=0.1, window=0.5, horizon=2.0, seed=2,
+                            log_mode="digest"))
+    sr.batch_run([tiny, other])
+    assert np.array_equal(ref.spins(), tiny.spins())
+    assert np.array_equal(ref.digests()[0], tiny.digests()[0])
+
+
+def test_batch_rejects_full_logs():
+    sr = _sr()
+    s = sr.Sim(W.params(32, 32, 8, 8, T=3.0, window=1.0, horizon=1.0, seed=4, log_mode="full"))
+    with pytest.raises(sr.SRError) as e:
+        sr.batch_run([s])
+    assert e.value.code == sr.SR_EINVAL
+
+
+def test_batch_no_convergence_reports():
+    sr = _sr()
+    p = W.params(32, 32, 8, 8, T=3.0, h=0.0, window=1.0, horizon=3.0, seed=4, max_iters=1,
+                 log_mode="digest")
+    s = sr.Sim(p)
+    with pytest.raises(sr.SRError) as e:
+        sr.batch_run([s])
+    assert e.value.code == sr.SR_ENOCONV
+    assert s.observables()["tick"] == 0
