@@ -49,7 +49,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--temps", default=None, help="comma list, default all three")
+    ap.add_argument("--horizon", type=float, default=100.0,
+                    help="shorter horizons only for profiler runs")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="run only a device-to-device copy of MB megabytes (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; "
                           "--gpus must be 1 (multi-GPU sharding is a design note, not built)"}))
@@ -63,7 +70,7 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     temps = W.MEDIUM_TEMPS if not args.temps else tuple(float(x) for x in args.temps.split(","))
-    ps = [W.medium(T=T) for T in temps]
+    ps = [W.medium(T=T, horizon=args.horizon) for T in temps]
     sims = [sr.Sim(dict(p, log_mode="digest"), stream=stream) for p in ps]
 
     def step():
@@ -129,8 +136,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "medium: 1024x1024 periodic Ising, J=1, h=0.1, "
                                f"T in {list(temps)}, Metropolis, random +-1 start, 4096 "
-                               "subdomains of 16x16, window 0.5, horizon 100",
-                   "lattices": len(sims), "horizon": 100.0, "window": 0.5},
+                               f"subdomains of 16x16, window 0.5, horizon {args.horizon:g}",
+                   "lattices": len(sims), "horizon": args.horizon, "window": 0.5},
         "committed_flips_per_step": int(flips),
         "processed_per_committed": round(processed / max(flips, 1), 3),
         "relax_iters_per_window": round(float(gs.mean()), 3),
@@ -154,6 +161,18 @@ def main():
         line["cpu_baseline"] = cpu_baseline(sr, W, stream, temps)
 
     print(json.dumps(line), flush=True)
+
+
+def copy_calibration(mb):
+    """A plain device copy of known size, to scale the HBM byte counters."""
+    import torch
+    n = mb * (1 << 20)
+    x = torch.ones(n, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n, "launches": 3}))
 
 
 def bench_batch(sr, W, stream, torch, n=512, horizon=50.0):

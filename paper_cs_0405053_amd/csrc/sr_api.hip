@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -28,6 +29,7 @@ hipError_t launch_fill(int8_t* s, int64_t n, int8_t v, hipStream_t stream);
 hipError_t launch_observables(const int8_t* s, int Lx, int Ly, unsigned long long* out,
                               hipStream_t stream);
 hipError_t launch_batch(const BatchArgs& B, int waves, size_t lds, hipStream_t stream);
+hipError_t build_window_graph(const Lattice& L, const Step* dstep, int k, hipGraphExec_t* out);
 int batch_waves_per_cu(size_t lds);
 }  // namespace sr
 
@@ -49,6 +51,12 @@ struct sr_sim {
   double relax_ms = 0.0;
   int64_t batch_tasks = 0;
   double last_batch_ms = 0.0;
+  // captured windows: graph of k iterations, keyed by k (rebuilt when the
+  // buffers move); the window descriptor is read from dstep
+  bool use_graphs = true;
+  Step* dstep = nullptr;
+  Step* hstep = nullptr;
+  std::vector<std::pair<int, hipGraphExec_t>> graphs;
   IterFlags* hflags = nullptr;         // pinned host mirror of the flags
   std::vector<std::vector<int64_t>> log_tick, log_site;   // SR_LOG_FULL
   std::string err;
@@ -140,7 +148,13 @@ extern "C" int sr_tune(const sr_params* p, int32_t* bx, int32_t* by, double* win
 }
 
 // ------------------------------------------------------------ buffers
+static void drop_graphs(sr_sim* s) {
+  for (auto& g : s->graphs) (void)hipGraphExecDestroy(g.second);
+  s->graphs.clear();
+}
+
 static void free_hist(sr_sim* s) {
+  drop_graphs(s);
   if (s->L.hist) (void)hipFree(s->L.hist);
   s->L.hist = nullptr;
   if (s->L.wlog) (void)hipFree(s->L.wlog);
@@ -171,6 +185,9 @@ static void free_all(sr_sim* s) {
   if (s->obs) (void)hipFree(s->obs);
   if (s->hflags) (void)hipHostFree(s->hflags);
   if (s->init_copy) (void)hipFree(s->init_copy);
+  if (s->dstep) (void)hipFree(s->dstep);
+  if (s->hstep) (void)hipHostFree(s->hstep);
+  s->dstep = nullptr; s->hstep = nullptr;
   for (auto& e : s->ev) {
     if (e) (void)hipEventDestroy(e);
     e = nullptr;
@@ -250,6 +267,12 @@ static int create_impl(const sr_params* pin, void* stream, sr_sim** out, bool in
   if (alloc_hist(s) != SR_OK) return fail(SR_ENOMEM, "cannot allocate boundary lists");
   for (auto& e : s->ev)
     if (hipEventCreate(&e) != hipSuccess) return fail(SR_EDEVICE, "cannot create events");
+  if (hipMalloc(&s->dstep, sizeof(Step)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate step");
+  if (hipHostMalloc(&s->hstep, sizeof(Step), hipHostMallocDefault) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate pinned step");
+  {
+    const char* ng = std::getenv("SR_NO_GRAPHS");
+    s->use_graphs = !(ng && ng[0] == '1');
+  }
   if (p.init == SR_INIT_USER && init_state) {
     if (hipMalloc(&s->init_copy, nsite) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate initial spins");
   }
@@ -343,23 +366,44 @@ static int run_one_window(sr_sim* s, int32_t* g_out) {
   s->st.t_end = std::min(s->st.t_c + s->W, s->H);
   uint32_t fmax = 0;
   int it = 0;
-  int K = std::max(2, std::min(kMaxBatch, s->batch_hint));
+  // power-of-two batch sizes, so that few graphs cover every window
+  int K = 2;
+  while (K < s->batch_hint && K < kMaxBatch) K <<= 1;
   while (it < s->p.max_iters) {
     int k = std::min(K, s->p.max_iters - it);
-    HIP_OR_FAIL(s, hipMemsetAsync(L.flags, 0, (size_t)k * sizeof(IterFlags), s->stream));
-    for (int i = 0; i < k; ++i) {
-      Step st = s->st;
-      st.it = it + i;
-      st.fi = i;
-      HIP_OR_FAIL(s, hipEventRecord(s->ev[2 * i], s->stream));
-      HIP_OR_FAIL(s, launch_relax(L, st, s->stream));
-      HIP_OR_FAIL(s, hipEventRecord(s->ev[2 * i + 1], s->stream));
+    if (s->use_graphs) {
+      hipGraphExec_t ge = nullptr;
+      for (auto& g : s->graphs)
+        if (g.first == k) ge = g.second;
+      if (!ge) {
+        if (s->graphs.size() >= 8) drop_graphs(s);
+        HIP_OR_FAIL(s, build_window_graph(L, s->dstep, k, &ge));
+        s->graphs.push_back({k, ge});
+      }
+      Step hs = s->st;
+      hs.it = it;
+      hs.fi = 0;
+      *s->hstep = hs;
+      HIP_OR_FAIL(s, hipMemcpyAsync(s->dstep, s->hstep, sizeof(Step), hipMemcpyHostToDevice, s->stream));
+      HIP_OR_FAIL(s, hipEventRecord(s->ev[0], s->stream));
+      HIP_OR_FAIL(s, hipGraphLaunch(ge, s->stream));
+      HIP_OR_FAIL(s, hipEventRecord(s->ev[1], s->stream));
+    } else {
+      HIP_OR_FAIL(s, hipMemsetAsync(L.flags, 0, (size_t)k * sizeof(IterFlags), s->stream));
+      HIP_OR_FAIL(s, hipEventRecord(s->ev[0], s->stream));
+      for (int i = 0; i < k; ++i) {
+        Step st = s->st;
+        st.it = it + i;
+        st.fi = i;
+        HIP_OR_FAIL(s, launch_relax(L, st, s->stream));
+      }
+      HIP_OR_FAIL(s, hipEventRecord(s->ev[1], s->stream));
     }
     HIP_OR_FAIL(s, hipMemcpyAsync(s->hflags, L.flags, (size_t)k * sizeof(IterFlags), hipMemcpyDeviceToHost, s->stream));
     HIP_OR_FAIL(s, hipStreamSynchronize(s->stream));
-    for (int i = 0; i < k; ++i) {
+    {
       float ms = 0.f;
-      HIP_OR_FAIL(s, hipEventElapsedTime(&ms, s->ev[2 * i], s->ev[2 * i + 1]));
+      HIP_OR_FAIL(s, hipEventElapsedTime(&ms, s->ev[0], s->ev[1]));
       s->relax_ms += ms;
     }
     s->relax_launches += k;

@@ -22,6 +22,8 @@
 //     comparison) and of the lists / event log being written (flushed with
 //     coalesced stores).
 // Nothing on the event chain touches HBM except chunk refills and flushes.
+#include <vector>
+
 #include "sr_internal.h"
 
 namespace sr {
@@ -532,6 +534,40 @@ __global__ __launch_bounds__(64) void relax_kernel(Lattice L, Step st) {
   relax_subdomain(L, st, d, tile, L.flags + st.fi);
 }
 
+// Graph form of the plain iteration: the window descriptor lives in device
+// memory (written by the host before each replay) and node i of the graph is
+// iteration st.it + i.
+__global__ __launch_bounds__(64) void relax_graph_kernel(Lattice L, const Step* stp, int i) {
+  extern __shared__ int8_t tile[];
+  const int d = blockIdx.x;
+  if (d >= L.nsub) return;
+  typedef const __attribute__((address_space(4))) Step CStep;
+  CStep& cs = *(CStep*)stp;
+  Step st;
+  st.t_c = cs.t_c; st.t_end = cs.t_end; st.wp = cs.wp; st.it = cs.it + i; st.fi = i; st.pad = 0;
+  if (i > 0) {
+    const IterFlags* fp = L.flags + i - 1;
+    if (fp->changed == 0 || fp->overflow != 0) return;
+  }
+  if (st.it > 0 && !inputs_changed(L, st.it, d)) {
+    if (lane_id() == 0) {
+      slot_at(L, st.it & 1)[d] = slot_at(L, (st.it + 1) & 1)[d];
+      chg_at(L, st.it & 1)[d] = 0;
+    }
+    return;
+  }
+  relax_subdomain(L, st, d, tile, L.flags + i);
+}
+
+// Clears the first n iteration flags (a kernel, so that graphs hold no
+// memset nodes).
+__global__ void clear_flags_kernel(IterFlags* f, int n) {
+  int i = threadIdx.x;
+  if (i < n) {
+    f[i].changed = 0; f[i].overflow = 0; f[i].fmax = 0; f[i].pad0 = 0; f[i].events = 0;
+  }
+}
+
 // ------------------------------------------------------------ batched form
 // Per-lattice descriptors are read through the constant address space: they
 // do not change while the kernel runs, so the compiler may keep their fields
@@ -737,6 +773,48 @@ hipError_t launch_relax(const Lattice& L, const Step& st, hipStream_t stream) {
   lds = (lds + 15) & ~(size_t)15;
   hipLaunchKernelGGL(relax_kernel, dim3(L.nsub), dim3(64), lds, stream, L, st);
   return hipGetLastError();
+}
+
+// A graph of k iterations of one window: clear the flags, then k relaxation
+// kernels in sequence.
+hipError_t build_window_graph(const Lattice& L, const Step* dstep, int k, hipGraphExec_t* out) {
+  hipGraph_t g = nullptr;
+  hipError_t e = hipGraphCreate(&g, 0);
+  if (e != hipSuccess) return e;
+  hipGraphNode_t prev = nullptr, node = nullptr;
+  IterFlags* fl = L.flags;
+  int nclear = k;
+  void* cargs[] = {&fl, &nclear};
+  hipKernelNodeParams kp = {};
+  kp.func = (void*)clear_flags_kernel;
+  kp.gridDim = dim3(1);
+  kp.blockDim = dim3(kMaxBatch);
+  kp.sharedMemBytes = 0;
+  kp.kernelParams = cargs;
+  kp.extra = nullptr;
+  e = hipGraphAddKernelNode(&node, g, nullptr, 0, &kp);
+  prev = node;
+  Lattice Lc = L;
+  const Step* sp = dstep;
+  std::vector<int> idx(k);
+  size_t lds = (size_t)(L.bx + 2) * (L.by + 2);
+  lds = (lds + 15) & ~(size_t)15;
+  for (int i = 0; i < k && e == hipSuccess; ++i) {
+    idx[i] = i;
+    void* rargs[] = {&Lc, &sp, &idx[i]};
+    hipKernelNodeParams rp = {};
+    rp.func = (void*)relax_graph_kernel;
+    rp.gridDim = dim3(L.nsub);
+    rp.blockDim = dim3(64);
+    rp.sharedMemBytes = (unsigned)lds;
+    rp.kernelParams = rargs;
+    rp.extra = nullptr;
+    e = hipGraphAddKernelNode(&node, g, &prev, 1, &rp);
+    prev = node;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  return e;
 }
 
 hipError_t launch_batch(const BatchArgs& B, int waves, size_t lds, hipStream_t stream) {
