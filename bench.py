@@ -113,9 +113,14 @@ def main():
                 "avg_launch_us": round(avg_launch_s * 1e6, 2), "launches_per_step": launches}
     traffic_file = os.path.join(ROOT, "profiles", "relax_kernel_medium_traffic.json")
     if os.path.exists(traffic_file):
+        import hashlib
         with open(traffic_file) as f:
             tr = json.load(f)
-        roofline["traffic"] = tr.get("bytes_per_launch")
+        with open(os.path.join(ROOT, "paper_cs_0405053_amd", "csrc", "sr_kernels.hip"), "rb") as f:
+            cur = hashlib.sha256(f.read()).hexdigest()
+        # counters describe one version of the kernel: stale once it changed
+        if tr.get("kernel_source_sha256") == cur:
+            roofline["traffic"] = tr.get("bytes_per_launch")
         if roofline["traffic"]:
             gbps = roofline["traffic"] / avg_launch_s / 1e9
             roofline["hbm_GBps"] = round(gbps, 1)
