@@ -179,7 +179,11 @@ static void free_all(sr_sim* s) {
   if (L.hcnt) (void)hipFree(L.hcnt);
   if (L.slot) (void)hipFree(L.slot);
   if (L.chg) (void)hipFree(L.chg);
+  if (L.fct) (void)hipFree(L.fct);
+  if (L.ck) (void)hipFree(L.ck);
+  if (L.ckn) (void)hipFree(L.ckn);
   L.spins = nullptr; L.carry = nullptr; L.hcnt = nullptr; L.slot = nullptr; L.chg = nullptr;
+  L.fct = nullptr; L.ck = nullptr; L.ckn = nullptr;
   if (L.wcnt) (void)hipFree(L.wcnt);
   if (L.flags) (void)hipFree(L.flags);
   if (s->obs) (void)hipFree(s->obs);
@@ -247,6 +251,10 @@ static int create_impl(const sr_params* pin, void* stream, sr_sim** out, bool in
   L.wcap = (int)std::max(64.0, std::ceil((blk + 6.0 * std::sqrt(blk) + 32.0) / 64.0) * 64.0);
   if (p.hist_cap > 0) L.hcap = p.hist_cap;
   if (p.wlog_cap > 0) L.wcap = p.wlog_cap;
+  // checkpoints every 8 events or break points, enough for about 1.5x the
+  // largest expected number of events of a window
+  L.ckint = 8;
+  L.nck = (int)std::min(32.0, std::max(4.0, std::ceil(1.5 * blk / L.ckint) + 1.0));
 
   size_t nsite = (size_t)p.Lx * p.Ly;
   auto fail = [&](int code, const char* what) {
@@ -260,6 +268,9 @@ static int create_impl(const sr_params* pin, void* stream, sr_sim** out, bool in
   if (hipMalloc(&L.hcnt, 2 * (size_t)L.nsub * kEdges * sizeof(uint32_t)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate list counts");
   if (hipMalloc(&L.slot, 2 * (size_t)L.nsub) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate slots");
   if (hipMalloc(&L.chg, 2 * (size_t)L.nsub) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate change flags");
+  if (hipMalloc(&L.fct, 2 * (size_t)L.nsub * kEdges * sizeof(int64_t)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate change ticks");
+  if (hipMalloc(&L.ck, (size_t)L.nsub * L.nck * sizeof(Ckpt)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate checkpoints");
+  if (hipMalloc(&L.ckn, (size_t)L.nsub * sizeof(uint32_t)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate checkpoint counts");
   if (hipMalloc(&L.wcnt, (size_t)L.nsub * sizeof(uint32_t)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate log counts");
   if (hipMalloc(&L.flags, kMaxBatch * sizeof(IterFlags)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate flags");
   if (hipMalloc(&s->obs, 4 * sizeof(unsigned long long)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate scratch");

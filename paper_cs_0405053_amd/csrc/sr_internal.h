@@ -25,6 +25,23 @@ struct alignas(64) Carry {
   int64_t pad[2];
 };
 
+// Snapshot of one subdomain's simulation state inside a window: the state
+// after every event and break point with tick < T.  A later iteration whose
+// inputs first differ at tick >= T resumes here instead of at the window
+// start (same inputs before T give the same state at T).
+struct alignas(256) Ckpt {
+  uint64_t cls[64];        // class nibbles, one word per lane
+  uint32_t ncnt[16];       // class counts N_k (k < 10)
+  int64_t T;
+  uint64_t j, acc;
+  int64_t anchor;
+  uint64_t halo[4];        // N, S, W, E halo spins
+  uint64_t dsum;           // digest sum of the window-log entries flushed so far
+  int32_t nev, nbound;     // window events so far, of which on the boundary
+  int32_t nout[4];         // own boundary-list lengths
+  int32_t head[4];         // input-list positions
+};
+
 // Per-iteration flags, cleared before every iteration.
 struct IterFlags {
   uint32_t changed;      // some boundary history differs from the previous iteration
@@ -52,6 +69,12 @@ struct Lattice {
   uint8_t* slot;          // 2 x nsub: slot holding a subdomain's latest lists,
                           // by iteration parity
   uint8_t* chg;           // 2 x nsub: lists changed in that iteration, by parity
+  int64_t* fct;           // 2 x [nsub][4]: per slot, first tick at which a list
+                          // differs from its previous version (kTickInf: same)
+  Ckpt* ck;               // [nsub][nck] checkpoints of each subdomain's last run
+  uint32_t* ckn;          // [nsub] valid checkpoints of that run
+  int32_t nck;            // checkpoints per subdomain and window
+  int32_t ckint;          // events + break points between checkpoints
   uint64_t* wlog;         // [nsub][wcap]: tick << 16 | local site
   uint32_t* wcnt;         // [nsub]
   IterFlags* flags;       // [kMaxBatch], one per queued iteration
@@ -78,6 +101,10 @@ template <class LT>
 __host__ __device__ inline uint8_t* slot_at(const LT& L, int q) { return L.slot + (q & 1) * L.nsub; }
 template <class LT>
 __host__ __device__ inline uint8_t* chg_at(const LT& L, int q) { return L.chg + (q & 1) * L.nsub; }
+template <class LT>
+__host__ __device__ inline int64_t* fct_at(const LT& L, int q) {
+  return L.fct + (q & 1) * (L.nsub * kEdges);
+}
 
 // Where a lattice stands in its window loop.
 struct Step {

@@ -160,10 +160,12 @@ struct ListIn {
   uint64_t chunk;
   int64_t ht;          // tick of the head entry, kTickInf when exhausted
 };
-__device__ __forceinline__ void list_open(ListIn& s, const uint64_t* p, int n, int lane) {
-  s.p = p; s.n = n; s.head = 0;
-  s.chunk = (lane < n) ? p[lane] : ~0ull;
-  s.ht = n > 0 ? (int64_t)(rdl64(s.chunk, 0) >> kPosBits) : kTickInf;
+// Open at position `head` (entries before it are taken as consumed).
+__device__ __forceinline__ void list_open(ListIn& s, const uint64_t* p, int n, int head, int lane) {
+  s.p = p; s.n = n; s.head = head;
+  int b = head & ~63;
+  s.chunk = (b + lane < n) ? p[b + lane] : ~0ull;
+  s.ht = head < n ? (int64_t)(rdl64(s.chunk, head & 63) >> kPosBits) : kTickInf;
 }
 // Returns the head entry and advances.
 __device__ __forceinline__ uint64_t list_pop(ListIn& s, int lane) {
@@ -179,26 +181,36 @@ __device__ __forceinline__ uint64_t list_pop(ListIn& s, int lane) {
 }
 
 // An own boundary list being written: buffered 64 entries at a time, and
-// compared entry by entry with the same list of the previous iteration.
+// compared entry by entry with the same list of the previous iteration
+// (`fct` = first tick at which the two differ).
 struct ListOut {
   uint64_t* p;
   int cap, n;
   uint64_t buf;
   ListIn prev;
-  bool diff;
+  int64_t fct;
 };
+// Resume at length n0: the first n0 entries equal those of the previous
+// version `prev`; copy them over and reload the open 64-entry chunk.
 __device__ __forceinline__ void out_open(ListOut& o, uint64_t* p, int cap, const uint64_t* prev,
-                                         int nprev, int lane) {
-  o.p = p; o.cap = cap; o.n = 0; o.buf = 0; o.diff = false;
-  list_open(o.prev, prev, nprev, lane);
+                                         int nprev, int n0, int lane) {
+  o.p = p; o.cap = cap; o.n = n0; o.fct = kTickInf;
+  for (int i = lane; i < (n0 & ~63); i += 64) p[i] = prev[i];
+  int b = n0 & ~63;
+  o.buf = (b + lane < n0) ? prev[b + lane] : 0ull;
+  list_open(o.prev, prev, nprev, n0, lane);
 }
 __device__ __forceinline__ void out_push(ListOut& o, uint64_t x, int lane) {
   int k = o.n & 63;
   if (lane == k) o.buf = x;
-  if (o.n < o.prev.n) {
-    if (list_pop(o.prev, lane) != x) o.diff = true;
-  } else {
-    o.diff = true;
+  if (o.fct == kTickInf) {
+    int64_t tx = (int64_t)(x >> kPosBits);
+    if (o.n < o.prev.n) {
+      int64_t tp = o.prev.ht;
+      if (list_pop(o.prev, lane) != x) o.fct = tx < tp ? tx : tp;
+    } else {
+      o.fct = tx;
+    }
   }
   o.n++;
   if ((o.n & 63) == 0) {
@@ -210,7 +222,8 @@ __device__ __forceinline__ void out_close(ListOut& o, int lane) {
   int k = o.n & 63;
   int at = o.n - k + lane;
   if (lane < k && at < o.cap) o.p[at] = o.buf;
-  if (o.n != o.prev.n) o.diff = true;
+  // a shorter list differs at its first missing entry
+  if (o.fct == kTickInf && o.n < o.prev.n) o.fct = o.prev.ht;
 }
 
 // SplitMix64 finaliser (Steele, Lea & Flood 2014) for event digests.
@@ -230,7 +243,8 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
 }
 
 // ------------------------------------------------------------ relaxation
-// One subdomain (this wave) over one window, one iteration.
+// One subdomain (this wave) over one window, one iteration (Sec. 4 box, step
+// (a) for one PE; Sec. 5 for the Ising specifics).
 template <class LT>
 __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int d,
                                                 int8_t* tile, IterFlags* fl) {
@@ -241,7 +255,7 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
   const int x0 = cx * bx, y0 = cy * by;
   const int nblk = bx * by;
   const bool wrapx = (nbx == 1), wrapy = (nby == 1);
-  const int first = (st.it == 0);
+  const bool first = (st.it == 0);
   const int hcap = L.hcap;
   const int dn = ((cy + nby - 1) % nby) * nbx + cx;
   const int ds = ((cy + 1) % nby) * nbx + cx;
@@ -252,64 +266,101 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
   uint8_t* chg_now = chg_at(L, st.it & 1);
   const uint8_t* chg_prev = chg_at(L, (st.it + 1) & 1);
   const int sprev = first ? 0 : slot_prev[d];
-  (void)chg_prev;
   const int sout = first ? 0 : 1 - sprev;
-  const int8_t* sp = spins_at(L, st.wp);
-  const int tw = bx + 2;
+  const Carry* cin = &carry_at(L, st.wp)[d];
+  const uint32_t k0 = L.seed_lo, k1 = L.seed_hi;
+  auto clampn = [&](uint32_t n) { return (int)(n < (uint32_t)hcap ? n : (uint32_t)hcap); };
 
-  // committed block + one-site halo -> LDS (internal wrap falls out of the
-  // periodic global index when the block spans the torus)
-  for (int i = lane; i < (by + 2) * tw; i += 64) {
-    int ty = i / tw, tx = i - ty * tw;
-    int gy = y0 + ty - 1, gx = x0 + tx - 1;
-    gy = gy < 0 ? gy + L.Ly : (gy >= L.Ly ? gy - L.Ly : gy);
-    gx = gx < 0 ? gx + L.Lx : (gx >= L.Lx ? gx - L.Lx : gx);
-    tile[i] = sp[(int64_t)gy * L.Lx + gx];
-  }
-  __syncthreads();
-
-  // classes of owned sites, 4 bits each; unused nibbles hold 0xF
-  uint64_t cls = ~0ull;
-  const int base = lane << sh;
-  for (int i = 0; i < S; ++i) {
-    int v = base + i;
-    if (v < nblk) {
-      int ly = v / bx, lx = v - ly * bx;
-      int tp = (ly + 1) * tw + lx + 1;
-      int up = (tile[tp - 1] > 0) + (tile[tp + 1] > 0) + (tile[tp - tw] > 0) + (tile[tp + tw] > 0);
-      int k = (tile[tp] < 0 ? 5 : 0) + up;
-      cls = (cls & ~(0xFull << (4 * i))) | ((uint64_t)k << (4 * i));
-    }
-  }
-  // halo spins (bit p set = up) of the four external directions
-  uint64_t hN = ballot(lane < bx && tile[lane + 1] > 0);
-  uint64_t hS = ballot(lane < bx && tile[(by + 1) * tw + lane + 1] > 0);
-  uint64_t hW = ballot(lane < by && tile[(lane + 1) * tw] > 0);
-  uint64_t hE = ballot(lane < by && tile[(lane + 1) * tw + bx + 1] > 0);
-
-  // class counts N_k in lane k
-  uint32_t ncnt = 0;
-  for (int k = 0; k < kClasses; ++k) {
-    uint64_t x = cls ^ (0x1111111111111111ull * (uint64_t)k);
-    uint64_t nz = (x | (x >> 1) | (x >> 2) | (x >> 3)) & 0x1111111111111111ull;
-    uint32_t c = (uint32_t)__popcll(~nz & 0x1111111111111111ull);
-    uint32_t tot = rdl(wave_incl_scan(c), 63);
-    if (lane == k) ncnt = tot;
-  }
   uint32_t rate = 0;
 #pragma unroll
   for (int k = 0; k < kClasses; ++k)
     if (lane == k) rate = L.rate[k];
 
-  // carry at committed time, presimulated randoms
-  const Carry* cin = &carry_at(L, st.wp)[d];
-  uint64_t j = cin->j, acc = cin->acc;
-  int64_t anchor = cin->anchor;
-  const uint32_t k0 = L.seed_lo, k1 = L.seed_hi;
+  // ---- where to start: the latest checkpoint of this subdomain's last run
+  // whose state only depends on input entries that did not change
+  int ck = -1;
+  if (!first) {
+    int64_t tau = kTickInf;
+    auto edge_change = [&](int e, int edge, bool none) {
+      if (none || !chg_prev[e]) return;
+      int64_t f = fct_at(L, slot_prev[e])[e * kEdges + edge];
+      tau = f < tau ? f : tau;
+    };
+    edge_change(dn, kS, wrapy);
+    edge_change(ds, kN, wrapy);
+    edge_change(dw, kE, wrapx);
+    edge_change(de, kW, wrapx);
+    const int nck = (int)L.ckn[d];
+    const Ckpt* cks = L.ck + (size_t)d * L.nck;
+    bool ok = lane < nck && cks[lane < nck ? lane : 0].T <= tau;
+    uint64_t m = ballot(ok);
+    if (m) ck = 63 - __builtin_clzll(m);
+  }
+
+  uint64_t cls, hN, hS, hW, hE, j, acc, dtot;
+  uint32_t ncnt;
+  int64_t anchor;
+  int nev, nbound, n0[4], h0[4];
+  if (ck >= 0) {
+    const Ckpt* c = L.ck + (size_t)d * L.nck + ck;
+    cls = c->cls[lane];
+    ncnt = lane < 16 ? c->ncnt[lane & 15] : 0u;
+    hN = c->halo[0]; hS = c->halo[1]; hW = c->halo[2]; hE = c->halo[3];
+    j = c->j; acc = c->acc; anchor = c->anchor; dtot = c->dsum;
+    nev = c->nev; nbound = c->nbound;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) { n0[e] = c->nout[e]; h0[e] = c->head[e]; }
+  } else {
+    // committed block + one-site halo -> LDS (internal wrap falls out of the
+    // periodic global index when the block spans the torus)
+    const int8_t* sp = spins_at(L, st.wp);
+    const int tw = bx + 2;
+    for (int i = lane; i < (by + 2) * tw; i += 64) {
+      int ty = i / tw, tx = i - ty * tw;
+      int gy = y0 + ty - 1, gx = x0 + tx - 1;
+      gy = gy < 0 ? gy + L.Ly : (gy >= L.Ly ? gy - L.Ly : gy);
+      gx = gx < 0 ? gx + L.Lx : (gx >= L.Lx ? gx - L.Lx : gx);
+      tile[i] = sp[(int64_t)gy * L.Lx + gx];
+    }
+    __syncthreads();
+    // classes of owned sites, 4 bits each; unused nibbles hold 0xF
+    cls = ~0ull;
+    const int base = lane << sh;
+    for (int i = 0; i < S; ++i) {
+      int v = base + i;
+      if (v < nblk) {
+        int ly = v / bx, lx = v - ly * bx;
+        int tp = (ly + 1) * tw + lx + 1;
+        int up = (tile[tp - 1] > 0) + (tile[tp + 1] > 0) + (tile[tp - tw] > 0) + (tile[tp + tw] > 0);
+        int k = (tile[tp] < 0 ? 5 : 0) + up;
+        cls = (cls & ~(0xFull << (4 * i))) | ((uint64_t)k << (4 * i));
+      }
+    }
+    // halo spins (bit p set = up) of the four external directions
+    hN = ballot(lane < bx && tile[lane + 1] > 0);
+    hS = ballot(lane < bx && tile[(by + 1) * tw + lane + 1] > 0);
+    hW = ballot(lane < by && tile[(lane + 1) * tw] > 0);
+    hE = ballot(lane < by && tile[(lane + 1) * tw + bx + 1] > 0);
+    // class counts N_k in lane k
+    ncnt = 0;
+    for (int k = 0; k < kClasses; ++k) {
+      uint64_t x = cls ^ (0x1111111111111111ull * (uint64_t)k);
+      uint64_t nz = (x | (x >> 1) | (x >> 2) | (x >> 3)) & 0x1111111111111111ull;
+      uint32_t c = (uint32_t)__popcll(~nz & 0x1111111111111111ull);
+      uint32_t tot = rdl(wave_incl_scan(c), 63);
+      if (lane == k) ncnt = tot;
+    }
+    j = cin->j; acc = cin->acc; anchor = cin->anchor; dtot = 0;
+    nev = 0; nbound = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) { n0[e] = 0; h0[e] = 0; }
+  }
+  const int nev0 = nev;
+
+  // presimulated randoms of the current 64-chunk
   uint64_t Eb, Vb;
   draw_chunk(k0, k1, j & ~63ull, (uint32_t)d, lane, L.tick_bits, Eb, Vb);
   uint64_t E = rdl64(Eb, (int)(j & 63)), V = rdl64(Vb, (int)(j & 63));
-
   uint64_t C = row_incl_scan64((uint64_t)ncnt * rate);
   uint64_t lam = rdl64(C, kClasses - 1);
   int64_t next = next_tick(anchor, E, acc, lam);
@@ -317,42 +368,46 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
   // neighbour histories of the previous iteration (break points), each in
   // the slot its owner last wrote; the first iteration assumes none
   // (canonical assumption)
-  auto clampn = [&](uint32_t n) { return (int)(n < (uint32_t)hcap ? n : (uint32_t)hcap); };
-  auto in_list = [&](ListIn& li, int e, int edge, bool none) {
+  auto in_list = [&](ListIn& li, int e, int edge, bool none, int head) {
     int q = none ? 0 : slot_prev[e];
     list_open(li, hist_at(L, q) + ((size_t)e * kEdges + edge) * hcap,
-              none ? 0 : clampn(hcnt_at(L, q)[e * kEdges + edge]), lane);
+              none ? 0 : clampn(hcnt_at(L, q)[e * kEdges + edge]), head, lane);
   };
   ListIn inN, inS, inW, inE;
-  in_list(inN, dn, kS, first || wrapy);
-  in_list(inS, ds, kN, first || wrapy);
-  in_list(inW, dw, kE, first || wrapx);
-  in_list(inE, de, kW, first || wrapx);
+  in_list(inN, dn, kS, first || wrapy, h0[0]);
+  in_list(inS, ds, kN, first || wrapy, h0[1]);
+  in_list(inW, dw, kE, first || wrapx, h0[2]);
+  in_list(inE, de, kW, first || wrapx, h0[3]);
 
   // own lists of this iteration (into the other slot), compared with the
   // ones of the previous iteration
-  auto own_list = [&](ListOut& lo, int edge) {
+  auto own_list = [&](ListOut& lo, int edge, int n_start) {
     out_open(lo, hist_at(L, sout) + ((size_t)d * kEdges + edge) * hcap, hcap,
              hist_at(L, sprev) + ((size_t)d * kEdges + edge) * hcap,
-             first ? 0 : clampn(hcnt_at(L, sprev)[d * kEdges + edge]), lane);
+             first ? 0 : clampn(hcnt_at(L, sprev)[d * kEdges + edge]), n_start, lane);
   };
   ListOut oN, oS, oW, oE;
-  own_list(oN, kN); own_list(oS, kS); own_list(oW, kW); own_list(oE, kE);
+  own_list(oN, kN, n0[0]); own_list(oS, kS, n0[1]); own_list(oW, kW, n0[2]); own_list(oE, kE, n0[3]);
 
   // window event log (tick << 16 | local site), buffered 64 at a time
   uint64_t* wl = L.wlog + (size_t)d * L.wcap;
   const int wcap = L.wcap;
-  uint64_t lbuf = 0, dsum = 0;
-  int nev = 0, nbound = 0;
+  uint64_t lbuf = 0;
+  {
+    int b = nev & ~63;
+    if (b + lane < nev && b + lane < wcap) lbuf = wl[b + lane];
+  }
   auto log_flush = [&](int k) {          // k buffered entries in lanes 0..k-1
     int at = nev - k + lane;
+    uint64_t dsum = 0;
     if (lane < k) {
       if (at < wcap) wl[at] = lbuf;
       int v = (int)(lbuf & 0xFFFF);
       int ly = v / bx, lx = v - ly * bx;
       int64_t g = (int64_t)(y0 + ly) * L.Lx + x0 + lx;
-      dsum += mix64(mix64(lbuf >> kPosBits) + (uint64_t)g);
+      dsum = mix64(mix64(lbuf >> kPosBits) + (uint64_t)g);
     }
+    dtot += wave_sum64(dsum);
   };
 
   // move site u (local) by `delta` classes
@@ -370,13 +425,36 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
   // window is re-run with more room anyway
   const int nev_limit = 4 * wcap + 64;
   bool runaway = false;
+  Ckpt* ckbase = L.ck + (size_t)d * L.nck;
+  int ckc = ck + 1;                      // next checkpoint slot
+  int since = 0;                         // items since the last checkpoint
+  int64_t last_t = -1;                   // tick of the last processed item
   for (;;) {
     if (nev >= nev_limit) { runaway = true; break; }
     int64_t tb = min64(min64(inN.ht, inS.ht), min64(inW.ht, inE.ht));
+    const int64_t tn = min64(next, tb);
+    if (tn >= t_end) break;
+    if (since >= L.ckint && ckc < L.nck && tn > last_t) {
+      // state after every item with tick < tn: a place to resume from
+      Ckpt* c = ckbase + ckc;
+      c->cls[lane] = cls;
+      if (lane < 16) c->ncnt[lane] = ncnt;
+      if (lane == 0) {
+        c->T = tn; c->j = j; c->acc = acc; c->anchor = anchor;
+        c->halo[0] = hN; c->halo[1] = hS; c->halo[2] = hW; c->halo[3] = hE;
+        c->dsum = dtot;                  // log entries flushed so far
+        c->nev = nev; c->nbound = nbound;
+        c->nout[0] = oN.n; c->nout[1] = oS.n; c->nout[2] = oW.n; c->nout[3] = oE.n;
+        c->head[0] = inN.head; c->head[1] = inS.head; c->head[2] = inW.head; c->head[3] = inE.head;
+      }
+      ckc++;
+      since = 0;
+    }
+    since++;
     if (next <= tb) {
       // ---- own event (first on a tie: it chooses from the pre-tick state)
-      if (next >= t_end) break;
       const int64_t t = next;
+      last_t = t;
       // class: first k with C_k > target (eqs. Wsum, Wstop)
       uint64_t target = __umul64hi(V, lam);
       uint64_t gt = ballot(lane < kClasses && C > target);
@@ -435,8 +513,8 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
       next = next_tick(anchor, E, acc, lam);
     } else {
       // ---- break point: a neighbour flip changes our halo (Sec. 5)
-      if (tb >= t_end) break;
       const int64_t t = tb;
+      last_t = t;
       if (inN.ht == tb) {
         int p = (int)(list_pop(inN, lane) & 0xFFFF);
         hN ^= 1ull << p;
@@ -468,26 +546,31 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
 
   // end-of-window block -> working lattice (the other window parity)
   int8_t* so = spins_at(L, st.wp ^ 1);
-  for (int i = 0; i < S; ++i) {
-    int v = base + i;
-    if (v < nblk) {
-      int ly = v / bx, lx = v - ly * bx;
-      int k = (int)((cls >> (4 * i)) & 15);
-      so[(int64_t)(y0 + ly) * L.Lx + x0 + lx] = (int8_t)(k < 5 ? 1 : -1);
+  {
+    const int base = lane << sh;
+    for (int i = 0; i < S; ++i) {
+      int v = base + i;
+      if (v < nblk) {
+        int ly = v / bx, lx = v - ly * bx;
+        int k = (int)((cls >> (4 * i)) & 15);
+        so[(int64_t)(y0 + ly) * L.Lx + x0 + lx] = (int8_t)(k < 5 ? 1 : -1);
+      }
     }
   }
-  uint64_t dtot = wave_sum64(dsum);
   uint32_t* cnt_out = hcnt_at(L, sout) + d * kEdges;
+  int64_t* fct_out = fct_at(L, sout) + d * kEdges;
   if (lane == 0) {
     cnt_out[kN] = (uint32_t)oN.n; cnt_out[kS] = (uint32_t)oS.n;
     cnt_out[kW] = (uint32_t)oW.n; cnt_out[kE] = (uint32_t)oE.n;
+    fct_out[kN] = oN.fct; fct_out[kS] = oS.fct; fct_out[kW] = oW.fct; fct_out[kE] = oE.fct;
     Carry* co = &carry_at(L, st.wp ^ 1)[d];
     co->j = j; co->anchor = anchor; co->acc = acc;
     co->digest = cin->digest + dtot;
     co->flips = cin->flips + nev;
     co->wflips = nev;
     L.wcnt[d] = (uint32_t)nev;
-    bool changed = oN.diff || oS.diff || oW.diff || oE.diff;
+    L.ckn[d] = (uint32_t)ckc;
+    bool changed = oN.fct != kTickInf || oS.fct != kTickInf || oW.fct != kTickInf || oE.fct != kTickInf;
     slot_now[d] = (uint8_t)sout;
     chg_now[d] = changed ? 1 : 0;
     uint32_t ovf = ((oN.n > hcap || oS.n > hcap || oW.n > hcap || oE.n > hcap) ? 1u : 0u) |
@@ -495,7 +578,7 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
     if (changed) atomicOr(&fl->changed, 1u);
     if (ovf) atomicOr(&fl->overflow, ovf);
     atomicMax(&fl->fmax, (uint32_t)nbound);
-    atomicAdd(&fl->events, (unsigned long long)nev);
+    atomicAdd(&fl->events, (unsigned long long)(nev - nev0));
   }
 }
 
