@@ -99,6 +99,7 @@ def main():
     processed = sum(o["events_processed"] for g, o, d in results[-1])
     gs = np.concatenate([g for g, o, d in results[-1]])
     launches = sum(o["relax_launches"] for g, o, d in results[-1])
+    runs = sum(o["subdomain_runs"] for g, o, d in results[-1])
     relax_ms = sum(o["relax_ms"] for g, o, d in results[-1])
     repeat_exact = all(np.array_equal(a[2], b[2]) for r in results for a, b in zip(r, results[0]))
     nsub = results[-1][0][1]["n_sub"]
@@ -109,7 +110,7 @@ def main():
     achieved = instr_per_launch / avg_launch_s / 1e9
     roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(PEAK_WAVE_INSTR / 1e9, 1),
                 "unit": "Gwave-instr/s", "frac": round(achieved * 1e9 / PEAK_WAVE_INSTR, 4),
-                "traffic": None, "kernel": "relax_kernel",
+                "traffic": None, "kernel": "relax_graph_kernel",
                 "avg_launch_us": round(avg_launch_s * 1e6, 2), "launches_per_step": launches}
     traffic_file = os.path.join(ROOT, "profiles", "relax_kernel_medium_traffic.json")
     if os.path.exists(traffic_file):
@@ -145,6 +146,7 @@ def main():
                    "lattices": len(sims), "horizon": args.horizon, "window": 0.5},
         "committed_flips_per_step": int(flips),
         "processed_per_committed": round(processed / max(flips, 1), 3),
+        "events_per_subdomain_run": round(processed / max(runs, 1), 2),
         "relax_iters_per_window": round(float(gs.mean()), 3),
         "relax_iters_per_window_max": int(gs.max()),
         "ln_N": round(lnN, 3),

@@ -107,6 +107,8 @@ typedef struct {
   int64_t relax_launches;    /* relaxation-kernel launches so far */
   double relax_ms;           /* their summed device time (HIP events on the
                                 simulation's stream), milliseconds */
+  int64_t subdomain_runs;    /* subdomain-iterations actually simulated (the
+                                others kept their previous outputs) */
 } sr_obs;
 
 typedef struct sr_sim sr_sim;

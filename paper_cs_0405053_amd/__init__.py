@@ -57,7 +57,8 @@ class Obs(C.Structure):
                 ("tick_bits", C.c_int32), ("n_sub", C.c_int32), ("bx", C.c_int32),
                 ("by", C.c_int32), ("Lx", C.c_int32), ("Ly", C.c_int32),
                 ("window_ticks", C.c_int64), ("horizon_ticks", C.c_int64),
-                ("relax_launches", C.c_int64), ("relax_ms", C.c_double)]
+                ("relax_launches", C.c_int64), ("relax_ms", C.c_double),
+                ("subdomain_runs", C.c_int64)]
 
 
 _lib = None

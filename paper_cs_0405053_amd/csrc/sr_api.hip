@@ -41,7 +41,7 @@ struct sr_sim {
   Step st;
   hipStream_t stream = nullptr;
   int64_t W = 0, H = 0;             // window and horizon in ticks
-  int64_t windows = 0, iterations = 0, events = 0;
+  int64_t windows = 0, iterations = 0, events = 0, runs = 0;
   int32_t last_g = 0, last_f = 0;
   unsigned long long* obs = nullptr;   // device scratch for observables
   int8_t* init_copy = nullptr;         // initial spins for sr_reset (SR_INIT_USER)
@@ -422,6 +422,7 @@ static int run_one_window(sr_sim* s, int32_t* g_out) {
       const IterFlags& f = s->hflags[i];
       s->iterations++;
       s->events += (int64_t)f.events;
+      s->runs += f.runs;
       if (f.overflow) {
         int rc = grow(s, f.overflow);
         if (rc != SR_OK) return rc;
@@ -495,6 +496,7 @@ extern "C" int sr_observables(sr_sim* s, sr_obs* o) {
   o->horizon_ticks = s->H;
   o->relax_launches = s->relax_launches;
   o->relax_ms = s->relax_ms;
+  o->subdomain_runs = s->runs;
   return SR_OK;
 }
 
@@ -513,6 +515,7 @@ extern "C" int sr_reset(sr_sim* s) {
   s->last_g = s->last_f = 0;
   s->relax_launches = 0;
   s->relax_ms = 0.0;
+  s->runs = 0;
   for (auto& v : s->log_tick) v.clear();
   for (auto& v : s->log_site) v.clear();
   return SR_OK;
@@ -735,6 +738,7 @@ extern "C" int sr_batch_run(sr_sim* const* sims, int32_t n, void* stream_) {
     s->relax_launches += 1;
     s->relax_ms += ms;
     s->batch_tasks += r.tasks;
+    s->runs += r.tasks;
     int one = SR_OK;
     if (r.status == kOverflow) {
       // grow and finish alone from the last committed window

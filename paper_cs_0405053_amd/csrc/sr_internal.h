@@ -47,7 +47,7 @@ struct IterFlags {
   uint32_t changed;      // some boundary history differs from the previous iteration
   uint32_t overflow;     // some history / window-log buffer overflowed
   uint32_t fmax;         // max boundary-site events of one subdomain
-  uint32_t pad0;
+  uint32_t runs;         // subdomains that ran (the others kept their outputs)
   unsigned long long events;  // events simulated in this iteration
 };
 
@@ -68,7 +68,8 @@ struct Lattice {
   uint32_t* hcnt;         // 2 x [nsub][4]: list lengths, per slot
   uint8_t* slot;          // 2 x nsub: slot holding a subdomain's latest lists,
                           // by iteration parity
-  uint8_t* chg;           // 2 x nsub: lists changed in that iteration, by parity
+  uint8_t* chg;           // 2 x nsub: which of a subdomain's lists (bit per edge
+                          // N, S, W, E) changed in that iteration, by parity
   int64_t* fct;           // 2 x [nsub][4]: per slot, first tick at which a list
                           // differs from its previous version (kTickInf: same)
   Ckpt* ck;               // [nsub][nck] checkpoints of each subdomain's last run

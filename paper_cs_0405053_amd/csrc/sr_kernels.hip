@@ -140,6 +140,17 @@ __device__ __forceinline__ uint64_t udiv_floor(uint64_t n, uint64_t d, uint64_t*
   return q;
 }
 
+// floor(n / d) for a quotient below 2^20 (the index of a site inside its
+// class): a single-precision estimate, then exact integer correction.
+__device__ __forceinline__ uint32_t udiv_small(uint64_t n, uint32_t d) {
+  float qf = (float)n * __builtin_amdgcn_rcpf((float)d);
+  uint32_t q = (uint32_t)qf;
+  uint64_t p = (uint64_t)q * d;
+  while (p > n) { q -= 1; p -= d; }
+  while (n - p >= d) { q += 1; p += d; }
+  return q;
+}
+
 // Tick of the pending event: anchor + max(1, ceil((E - acc) / lam)), or never
 // when lam = 0 (eq. nextau, and eq. lambdataua after a break point).
 __device__ __forceinline__ int64_t next_tick(int64_t anchor, uint64_t E, uint64_t acc, uint64_t lam) {
@@ -282,7 +293,7 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
   if (!first) {
     int64_t tau = kTickInf;
     auto edge_change = [&](int e, int edge, bool none) {
-      if (none || !chg_prev[e]) return;
+      if (none || !(chg_prev[e] & (1u << edge))) return;
       int64_t f = fct_at(L, slot_prev[e])[e * kEdges + edge];
       tau = f < tau ? f : tau;
     };
@@ -461,8 +472,7 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
       int ks = ctz64(gt);
       uint64_t below = ks ? rdl64(C, ks - 1) : 0ull;
       uint32_t rk = rdl(rate, ks);
-      uint64_t nzr;
-      uint32_t idx = (uint32_t)udiv_floor(target - below, rk, &nzr);
+      uint32_t idx = udiv_small(target - below, rk);
       // site: the idx-th member of class ks in ascending local order
       // (eqs. nores, vindex)
       uint64_t x = cls ^ (0x1111111111111111ull * (uint64_t)ks);
@@ -570,9 +580,12 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
     co->wflips = nev;
     L.wcnt[d] = (uint32_t)nev;
     L.ckn[d] = (uint32_t)ckc;
-    bool changed = oN.fct != kTickInf || oS.fct != kTickInf || oW.fct != kTickInf || oE.fct != kTickInf;
+    const uint32_t emask = (oN.fct != kTickInf ? 1u << kN : 0u) | (oS.fct != kTickInf ? 1u << kS : 0u) |
+                           (oW.fct != kTickInf ? 1u << kW : 0u) | (oE.fct != kTickInf ? 1u << kE : 0u);
+    const bool changed = emask != 0;
     slot_now[d] = (uint8_t)sout;
-    chg_now[d] = changed ? 1 : 0;
+    chg_now[d] = (uint8_t)emask;
+    atomicAdd(&fl->runs, 1u);
     uint32_t ovf = ((oN.n > hcap || oS.n > hcap || oW.n > hcap || oE.n > hcap) ? 1u : 0u) |
                    ((nev > wcap || runaway) ? 2u : 0u);
     if (changed) atomicOr(&fl->changed, 1u);
@@ -589,10 +602,13 @@ template <class LT>
 __device__ __forceinline__ bool inputs_changed(const LT& L, int it, int d) {
   const int nbx = L.nbx, nby = L.nby;
   const int cx = d % nbx, cy = d / nbx;
+  // only the list of each neighbour's edge that faces d is an input of d
   const uint8_t* c = chg_at(L, (it + 1) & 1);
   bool need = false;
-  if (nby > 1) need |= (c[((cy + nby - 1) % nby) * nbx + cx] | c[((cy + 1) % nby) * nbx + cx]) != 0;
-  if (nbx > 1) need |= (c[cy * nbx + (cx + nbx - 1) % nbx] | c[cy * nbx + (cx + 1) % nbx]) != 0;
+  if (nby > 1)
+    need |= ((c[((cy + nby - 1) % nby) * nbx + cx] >> kS) & 1) | ((c[((cy + 1) % nby) * nbx + cx] >> kN) & 1);
+  if (nbx > 1)
+    need |= ((c[cy * nbx + (cx + nbx - 1) % nbx] >> kE) & 1) | ((c[cy * nbx + (cx + 1) % nbx] >> kW) & 1);
   return need;
 }
 
@@ -647,7 +663,7 @@ __global__ __launch_bounds__(64) void relax_graph_kernel(Lattice L, const Step* 
 __global__ void clear_flags_kernel(IterFlags* f, int n) {
   int i = threadIdx.x;
   if (i < n) {
-    f[i].changed = 0; f[i].overflow = 0; f[i].fmax = 0; f[i].pad0 = 0; f[i].events = 0;
+    f[i].changed = 0; f[i].overflow = 0; f[i].fmax = 0; f[i].runs = 0; f[i].events = 0;
   }
 }
 
@@ -676,7 +692,7 @@ __device__ __forceinline__ Step load_step(const Step* p) {
 __device__ __forceinline__ IterFlags load_flags(const IterFlags* p) {
   IterFlags f;
   f.changed = u32s(p->changed); f.overflow = u32s(p->overflow); f.fmax = u32s(p->fmax);
-  f.pad0 = 0;
+  f.runs = u32s(p->runs);
   f.events = (unsigned long long)u64s(reinterpret_cast<const int64_t&>(p->events));
   return f;
 }
@@ -773,7 +789,7 @@ __device__ void decide(const BatchArgs& B, int lat, int lane) {
   st.fi = 0;
   if (lane == 0) {
     run->st = st;
-    run->fl.changed = 0; run->fl.overflow = 0; run->fl.fmax = 0; run->fl.events = 0;
+    run->fl.changed = 0; run->fl.overflow = 0; run->fl.fmax = 0; run->fl.runs = 0; run->fl.events = 0;
   }
   enqueue_iteration(B, lat, run, L, next_it, lane);
 }
