@@ -31,6 +31,7 @@ hipError_t launch_observables(const int8_t* s, int Lx, int Ly, unsigned long lon
 hipError_t launch_batch(const BatchArgs& B, int waves, size_t lds, hipStream_t stream);
 hipError_t build_window_graph(const Lattice& L, const Step* dstep, int k, hipGraphExec_t* out);
 int batch_waves_per_cu(size_t lds);
+size_t relax_lds(const Lattice& L);
 }  // namespace sr
 
 using namespace sr;
@@ -332,7 +333,7 @@ extern "C" const char* sr_last_error(const sr_sim* s) {
 static int grow(sr_sim* s, uint32_t ovf) {
   Lattice& L = s->L;
   if (ovf & 1u) {
-    if (L.hcap >= (1 << 20)) SR_FAIL(s, SR_EOVERFLOW, "boundary list capacity limit reached");
+    if (L.hcap >= 1024) SR_FAIL(s, SR_EOVERFLOW, "boundary list capacity limit reached");
     L.hcap *= 2;
   }
   if (ovf & 2u) {
@@ -653,7 +654,7 @@ extern "C" int sr_batch_run(sr_sim* const* sims, int32_t n, void* stream_) {
     if (s->L.nsub >= (1 << 20)) SR_FAIL(s, SR_EINVAL, "too many subdomains for the batch queue");
     if (s->st.t_c >= s->H) continue;
     idx.push_back(i);
-    lds = std::max(lds, (size_t)((s->L.bx + 2) * (s->L.by + 2) + 15) & ~(size_t)15);
+    lds = std::max(lds, relax_lds(s->L));
     total += (uint64_t)s->L.nsub;
   }
   if (idx.empty()) return SR_OK;

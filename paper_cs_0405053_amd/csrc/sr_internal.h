@@ -39,7 +39,8 @@ struct alignas(256) Ckpt {
   uint64_t dsum;           // digest sum of the window-log entries flushed so far
   int32_t nev, nbound;     // window events so far, of which on the boundary
   int32_t nout[4];         // own boundary-list lengths
-  int32_t head[4];         // input-list positions
+  int32_t head;            // position in the merged neighbour-flip stream
+  int32_t pad[3];
 };
 
 // Per-iteration flags, cleared before every iteration.

@@ -164,77 +164,75 @@ __device__ __forceinline__ int64_t next_tick(int64_t anchor, uint64_t E, uint64_
 }
 
 // ------------------------------------------------------------ lists
-// A 64-entry window onto a sorted boundary list in HBM.
-struct ListIn {
-  const uint64_t* p;
+// The four neighbour lists of a subdomain are merged, once per run, into one
+// stream sorted by (tick, edge) in LDS; an entry is tick << 18 | edge << 16 |
+// position.  The event loop reads it through a 64-entry register window.
+constexpr int kKeyShift = 18;
+
+// Number of keys < k in the sorted LDS array a[0, n).
+__device__ __forceinline__ int lds_lower_bound(const uint64_t* a, int n, uint64_t k) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (a[mid] < k) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+struct Merged {
+  const uint64_t* m;   // LDS
   int n, head;
   uint64_t chunk;
   int64_t ht;          // tick of the head entry, kTickInf when exhausted
 };
-// Open at position `head` (entries before it are taken as consumed).
-__device__ __forceinline__ void list_open(ListIn& s, const uint64_t* p, int n, int head, int lane) {
-  s.p = p; s.n = n; s.head = head;
+__device__ __forceinline__ void merged_open(Merged& s, const uint64_t* m, int n, int head, int lane) {
+  s.m = m; s.n = n; s.head = head;
   int b = head & ~63;
-  s.chunk = (b + lane < n) ? p[b + lane] : ~0ull;
-  s.ht = head < n ? (int64_t)(rdl64(s.chunk, head & 63) >> kPosBits) : kTickInf;
+  s.chunk = (b + lane < n) ? m[b + lane] : ~0ull;
+  s.ht = head < n ? (int64_t)(rdl64(s.chunk, head & 63) >> kKeyShift) : kTickInf;
 }
-// Returns the head entry and advances.
-__device__ __forceinline__ uint64_t list_pop(ListIn& s, int lane) {
+__device__ __forceinline__ uint64_t merged_pop(Merged& s, int lane) {
   uint64_t e = rdl64(s.chunk, s.head & 63);
   s.head++;
   if (s.head >= s.n) {
     s.ht = kTickInf;
   } else {
-    if ((s.head & 63) == 0) s.chunk = (s.head + lane < s.n) ? s.p[s.head + lane] : ~0ull;
-    s.ht = (int64_t)(rdl64(s.chunk, s.head & 63) >> kPosBits);
+    if ((s.head & 63) == 0) s.chunk = (s.head + lane < s.n) ? s.m[s.head + lane] : ~0ull;
+    s.ht = (int64_t)(rdl64(s.chunk, s.head & 63) >> kKeyShift);
   }
   return e;
 }
 
-// An own boundary list being written: buffered 64 entries at a time, and
-// compared entry by entry with the same list of the previous iteration
-// (`fct` = first tick at which the two differ).
-struct ListOut {
-  uint64_t* p;
-  int cap, n;
-  uint64_t buf;
-  ListIn prev;
-  int64_t fct;
-};
-// Resume at length n0: the first n0 entries equal those of the previous
-// version `prev`; copy them over and reload the open 64-entry chunk.
-__device__ __forceinline__ void out_open(ListOut& o, uint64_t* p, int cap, const uint64_t* prev,
-                                         int nprev, int n0, int lane) {
-  o.p = p; o.cap = cap; o.n = n0; o.fct = kTickInf;
-  for (int i = lane; i < (n0 & ~63); i += 64) p[i] = prev[i];
-  int b = n0 & ~63;
-  o.buf = (b + lane < n0) ? prev[b + lane] : 0ull;
-  list_open(o.prev, prev, nprev, n0, lane);
-}
-__device__ __forceinline__ void out_push(ListOut& o, uint64_t x, int lane) {
-  int k = o.n & 63;
-  if (lane == k) o.buf = x;
-  if (o.fct == kTickInf) {
-    int64_t tx = (int64_t)(x >> kPosBits);
-    if (o.n < o.prev.n) {
-      int64_t tp = o.prev.ht;
-      if (list_pop(o.prev, lane) != x) o.fct = tx < tp ? tx : tp;
-    } else {
-      o.fct = tx;
+// First tick at which the own list just written (`cur`, n entries) differs
+// from the previous iteration's (`prev`, np entries); both agree on their
+// first n0 entries.  kTickInf if equal.  `cur` was written by this wave's
+// lanes: it is read with coherent loads after the caller's fence.
+__device__ __forceinline__ int64_t first_change(const uint64_t* cur, int n, const uint64_t* prev, int np,
+                                                int n0, int lane) {
+  const int m = n < np ? n : np;
+  for (int b = n0 & ~63; b < m; b += 64) {
+    int i = b + lane;
+    bool diff = false;
+    uint64_t x = 0, y = 0;
+    if (i >= n0 && i < m) {
+      x = __hip_atomic_load(&cur[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      y = prev[i];
+      diff = x != y;
+    }
+    uint64_t dm = ballot(diff);
+    if (dm) {
+      int f = ctz64(dm);
+      uint64_t xf = rdl64(x, f), yf = rdl64(y, f);
+      int64_t tx = (int64_t)(xf >> kPosBits), ty = (int64_t)(yf >> kPosBits);
+      return tx < ty ? tx : ty;
     }
   }
-  o.n++;
-  if ((o.n & 63) == 0) {
-    int at = o.n - 64 + lane;
-    if (at < o.cap) o.p[at] = o.buf;
-  }
-}
-__device__ __forceinline__ void out_close(ListOut& o, int lane) {
-  int k = o.n & 63;
-  int at = o.n - k + lane;
-  if (lane < k && at < o.cap) o.p[at] = o.buf;
-  // a shorter list differs at its first missing entry
-  if (o.fct == kTickInf && o.n < o.prev.n) o.fct = o.prev.ht;
+  if (n == np) return kTickInf;
+  // one list is a prefix of the other: the first extra entry
+  uint64_t e = 0;
+  if (lane == 0) e = n > np ? __hip_atomic_load(&cur[m], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : prev[m];
+  e = rdl64(e, 0);
+  return (int64_t)(e >> kPosBits);
 }
 
 // SplitMix64 finaliser (Steele, Lea & Flood 2014) for event digests.
@@ -253,12 +251,21 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
   return x;
 }
 
+// LDS bytes one relaxation wave needs: the halo tile, or the raw and merged
+// neighbour lists (4 lists of up to hcap entries each), whichever is larger.
+__host__ __device__ inline size_t relax_lds_bytes(int bx, int by, int hcap) {
+  size_t tile = (size_t)(bx + 2) * (by + 2);
+  size_t lists = (size_t)2 * 4 * hcap * sizeof(uint64_t);
+  size_t b = tile > lists ? tile : lists;
+  return (b + 15) & ~(size_t)15;
+}
+
 // ------------------------------------------------------------ relaxation
 // One subdomain (this wave) over one window, one iteration (Sec. 4 box, step
 // (a) for one PE; Sec. 5 for the Ising specifics).
 template <class LT>
 __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int d,
-                                                int8_t* tile, IterFlags* fl) {
+                                                int8_t* lds, IterFlags* fl) {
   const int lane = lane_id();
   const int bx = L.bx, by = L.by, sh = L.sshift, S = 1 << sh;
   const int nbx = L.nbx, nby = L.nby;
@@ -272,9 +279,7 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
   const int ds = ((cy + 1) % nby) * nbx + cx;
   const int dw = cy * nbx + (cx + nbx - 1) % nbx;
   const int de = cy * nbx + (cx + 1) % nbx;
-  uint8_t* slot_now = slot_at(L, st.it & 1);
   const uint8_t* slot_prev = slot_at(L, (st.it + 1) & 1);
-  uint8_t* chg_now = chg_at(L, st.it & 1);
   const uint8_t* chg_prev = chg_at(L, (st.it + 1) & 1);
   const int sprev = first ? 0 : slot_prev[d];
   const int sout = first ? 0 : 1 - sprev;
@@ -311,7 +316,7 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
   uint64_t cls, hN, hS, hW, hE, j, acc, dtot;
   uint32_t ncnt;
   int64_t anchor;
-  int nev, nbound, n0[4], h0[4];
+  int nev, nbound, n0[4], h0;
   if (ck >= 0) {
     const Ckpt* c = L.ck + (size_t)d * L.nck + ck;
     cls = c->cls[lane];
@@ -320,10 +325,12 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
     j = c->j; acc = c->acc; anchor = c->anchor; dtot = c->dsum;
     nev = c->nev; nbound = c->nbound;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) { n0[e] = c->nout[e]; h0[e] = c->head[e]; }
+    for (int e = 0; e < 4; ++e) n0[e] = c->nout[e];
+    h0 = c->head;
   } else {
     // committed block + one-site halo -> LDS (internal wrap falls out of the
     // periodic global index when the block spans the torus)
+    int8_t* tile = lds;
     const int8_t* sp = spins_at(L, st.wp);
     const int tw = bx + 2;
     for (int i = lane; i < (by + 2) * tw; i += 64) {
@@ -364,9 +371,72 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
     j = cin->j; acc = cin->acc; anchor = cin->anchor; dtot = 0;
     nev = 0; nbound = 0;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) { n0[e] = 0; h0[e] = 0; }
+    for (int e = 0; e < 4; ++e) n0[e] = 0;
+    h0 = 0;
+    __syncthreads();                     // the tile's LDS is reused below
   }
   const int nev0 = nev;
+
+  // ---- neighbour histories of the previous iteration (break points), each
+  // in the slot its owner last wrote; the first iteration assumes none
+  // (canonical assumption).  Merge the four into one stream in LDS.
+  uint64_t* raw = reinterpret_cast<uint64_t*>(lds);
+  uint64_t* mrg = raw + 4 * hcap;
+  int ni[4];
+  const uint64_t* li[4];
+  {
+    const int ev[4] = {dn, ds, dw, de};
+    const int ed[4] = {kS, kN, kE, kW};      // the neighbour's edge facing us
+    const bool none[4] = {first || wrapy, first || wrapy, first || wrapx, first || wrapx};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int sl = none[q] ? 0 : slot_prev[ev[q]];
+      li[q] = hist_at(L, sl) + ((size_t)ev[q] * kEdges + ed[q]) * hcap;
+      ni[q] = none[q] ? 0 : clampn(hcnt_at(L, sl)[ev[q] * kEdges + ed[q]]);
+    }
+  }
+  const int o1 = ni[0], o2 = o1 + ni[1], o3 = o2 + ni[2], tot = o3 + ni[3];
+  if (tot > 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int oq = q == 0 ? 0 : q == 1 ? o1 : q == 2 ? o2 : o3;
+      for (int i = lane; i < ni[q]; i += 64) {
+        uint64_t x = li[q][i];
+        raw[oq + i] = ((x >> kPosBits) << kKeyShift) | ((uint64_t)q << 16) | (x & 0xFFFF);
+      }
+    }
+    __syncthreads();
+    for (int i = lane; i < tot; i += 64) {
+      const int q = i < o1 ? 0 : i < o2 ? 1 : i < o3 ? 2 : 3;
+      const int oq = q == 0 ? 0 : q == 1 ? o1 : q == 2 ? o2 : o3;
+      const uint64_t key = raw[i];
+      int rank = i - oq;
+      if (q != 0) rank += lds_lower_bound(raw, ni[0], key);
+      if (q != 1) rank += lds_lower_bound(raw + o1, ni[1], key);
+      if (q != 2) rank += lds_lower_bound(raw + o2, ni[2], key);
+      if (q != 3) rank += lds_lower_bound(raw + o3, ni[3], key);
+      mrg[rank] = key;
+    }
+    __syncthreads();
+  }
+  Merged in;
+  merged_open(in, mrg, tot, h0, lane);
+
+  // ---- own lists of this iteration, written straight into the other slot
+  // (the previous version's first n0 entries copied over when resuming)
+  uint64_t* ob = hist_at(L, sout) + (size_t)d * kEdges * hcap;
+  const uint64_t* pb = hist_at(L, sprev) + (size_t)d * kEdges * hcap;
+  int np[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    np[e] = first ? 0 : clampn(hcnt_at(L, sprev)[d * kEdges + e]);
+    for (int i = lane; i < n0[e]; i += 64) ob[e * hcap + i] = pb[e * hcap + i];
+  }
+  int nN = n0[0], nS = n0[1], nW = n0[2], nE = n0[3];
+  auto push = [&](int e, int& n, uint64_t x) {
+    if (lane == 0 && n < hcap) ob[e * hcap + n] = x;
+    n++;
+  };
 
   // presimulated randoms of the current 64-chunk
   uint64_t Eb, Vb;
@@ -375,30 +445,6 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
   uint64_t C = row_incl_scan64((uint64_t)ncnt * rate);
   uint64_t lam = rdl64(C, kClasses - 1);
   int64_t next = next_tick(anchor, E, acc, lam);
-
-  // neighbour histories of the previous iteration (break points), each in
-  // the slot its owner last wrote; the first iteration assumes none
-  // (canonical assumption)
-  auto in_list = [&](ListIn& li, int e, int edge, bool none, int head) {
-    int q = none ? 0 : slot_prev[e];
-    list_open(li, hist_at(L, q) + ((size_t)e * kEdges + edge) * hcap,
-              none ? 0 : clampn(hcnt_at(L, q)[e * kEdges + edge]), head, lane);
-  };
-  ListIn inN, inS, inW, inE;
-  in_list(inN, dn, kS, first || wrapy, h0[0]);
-  in_list(inS, ds, kN, first || wrapy, h0[1]);
-  in_list(inW, dw, kE, first || wrapx, h0[2]);
-  in_list(inE, de, kW, first || wrapx, h0[3]);
-
-  // own lists of this iteration (into the other slot), compared with the
-  // ones of the previous iteration
-  auto own_list = [&](ListOut& lo, int edge, int n_start) {
-    out_open(lo, hist_at(L, sout) + ((size_t)d * kEdges + edge) * hcap, hcap,
-             hist_at(L, sprev) + ((size_t)d * kEdges + edge) * hcap,
-             first ? 0 : clampn(hcnt_at(L, sprev)[d * kEdges + edge]), n_start, lane);
-  };
-  ListOut oN, oS, oW, oE;
-  own_list(oN, kN, n0[0]); own_list(oS, kS, n0[1]); own_list(oW, kW, n0[2]); own_list(oE, kE, n0[3]);
 
   // window event log (tick << 16 | local site), buffered 64 at a time
   uint64_t* wl = L.wlog + (size_t)d * L.wcap;
@@ -442,7 +488,7 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
   int64_t last_t = -1;                   // tick of the last processed item
   for (;;) {
     if (nev >= nev_limit) { runaway = true; break; }
-    int64_t tb = min64(min64(inN.ht, inS.ht), min64(inW.ht, inE.ht));
+    const int64_t tb = in.ht;
     const int64_t tn = min64(next, tb);
     if (tn >= t_end) break;
     if (since >= L.ckint && ckc < L.nck && tn > last_t) {
@@ -455,8 +501,8 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
         c->halo[0] = hN; c->halo[1] = hS; c->halo[2] = hW; c->halo[3] = hE;
         c->dsum = dtot;                  // log entries flushed so far
         c->nev = nev; c->nbound = nbound;
-        c->nout[0] = oN.n; c->nout[1] = oS.n; c->nout[2] = oW.n; c->nout[3] = oE.n;
-        c->head[0] = inN.head; c->head[1] = inS.head; c->head[2] = inW.head; c->head[3] = inE.head;
+        c->nout[0] = nN; c->nout[1] = nS; c->nout[2] = nW; c->nout[3] = nE;
+        c->head = in.head;
       }
       ckc++;
       since = 0;
@@ -509,10 +555,10 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
       nev++;
       if ((nev & 63) == 0) log_flush(64);
       bool onb = false;
-      if (!wrapy && ly == 0) { out_push(oN, tk | (uint64_t)lx, lane); onb = true; }
-      if (!wrapy && ly == by - 1) { out_push(oS, tk | (uint64_t)lx, lane); onb = true; }
-      if (!wrapx && lx == 0) { out_push(oW, tk | (uint64_t)ly, lane); onb = true; }
-      if (!wrapx && lx == bx - 1) { out_push(oE, tk | (uint64_t)ly, lane); onb = true; }
+      if (!wrapy && ly == 0) { push(kN, nN, tk | (uint64_t)lx); onb = true; }
+      if (!wrapy && ly == by - 1) { push(kS, nS, tk | (uint64_t)lx); onb = true; }
+      if (!wrapx && lx == 0) { push(kW, nW, tk | (uint64_t)ly); onb = true; }
+      if (!wrapx && lx == bx - 1) { push(kE, nE, tk | (uint64_t)ly); onb = true; }
       nbound += onb;
       // next pair from the presimulated list
       j += 1; anchor = t; acc = 0;
@@ -525,20 +571,19 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
       // ---- break point: a neighbour flip changes our halo (Sec. 5)
       const int64_t t = tb;
       last_t = t;
-      if (inN.ht == tb) {
-        int p = (int)(list_pop(inN, lane) & 0xFFFF);
+      const uint64_t key = merged_pop(in, lane);
+      const int q = (int)((key >> 16) & 3);
+      const int p = (int)(key & 0xFFFF);
+      if (q == 0) {
         hN ^= 1ull << p;
         change(p, ((hN >> p) & 1) ? 1 : -1);
-      } else if (inS.ht == tb) {
-        int p = (int)(list_pop(inS, lane) & 0xFFFF);
+      } else if (q == 1) {
         hS ^= 1ull << p;
         change((by - 1) * bx + p, ((hS >> p) & 1) ? 1 : -1);
-      } else if (inW.ht == tb) {
-        int p = (int)(list_pop(inW, lane) & 0xFFFF);
+      } else if (q == 2) {
         hW ^= 1ull << p;
         change(p * bx, ((hW >> p) & 1) ? 1 : -1);
       } else {
-        int p = (int)(list_pop(inE, lane) & 0xFFFF);
         hE ^= 1ull << p;
         change(p * bx + bx - 1, ((hE >> p) & 1) ? 1 : -1);
       }
@@ -552,7 +597,6 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
     }
   }
   if (nev & 63) log_flush(nev & 63);
-  out_close(oN, lane); out_close(oS, lane); out_close(oW, lane); out_close(oE, lane);
 
   // end-of-window block -> working lattice (the other window parity)
   int8_t* so = spins_at(L, st.wp ^ 1);
@@ -567,12 +611,26 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
       }
     }
   }
+  // compare step (c): own lists against the previous iteration's
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  const int nn[4] = {nN, nS, nW, nE};
+  int64_t fc[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    fc[e] = first ? (nn[e] > 0 ? (int64_t)(__hip_atomic_load(&ob[e * hcap], __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT) >> kPosBits)
+                               : kTickInf)
+                  : first_change(ob + e * hcap, clampn((uint32_t)nn[e]), pb + e * hcap, np[e], n0[e], lane);
   uint32_t* cnt_out = hcnt_at(L, sout) + d * kEdges;
   int64_t* fct_out = fct_at(L, sout) + d * kEdges;
   if (lane == 0) {
-    cnt_out[kN] = (uint32_t)oN.n; cnt_out[kS] = (uint32_t)oS.n;
-    cnt_out[kW] = (uint32_t)oW.n; cnt_out[kE] = (uint32_t)oE.n;
-    fct_out[kN] = oN.fct; fct_out[kS] = oS.fct; fct_out[kW] = oW.fct; fct_out[kE] = oE.fct;
+    uint32_t emask = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      cnt_out[e] = (uint32_t)nn[e];
+      fct_out[e] = fc[e];
+      emask |= fc[e] != kTickInf ? 1u << e : 0u;
+    }
     Carry* co = &carry_at(L, st.wp ^ 1)[d];
     co->j = j; co->anchor = anchor; co->acc = acc;
     co->digest = cin->digest + dtot;
@@ -580,17 +638,14 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
     co->wflips = nev;
     L.wcnt[d] = (uint32_t)nev;
     L.ckn[d] = (uint32_t)ckc;
-    const uint32_t emask = (oN.fct != kTickInf ? 1u << kN : 0u) | (oS.fct != kTickInf ? 1u << kS : 0u) |
-                           (oW.fct != kTickInf ? 1u << kW : 0u) | (oE.fct != kTickInf ? 1u << kE : 0u);
-    const bool changed = emask != 0;
-    slot_now[d] = (uint8_t)sout;
-    chg_now[d] = (uint8_t)emask;
-    atomicAdd(&fl->runs, 1u);
-    uint32_t ovf = ((oN.n > hcap || oS.n > hcap || oW.n > hcap || oE.n > hcap) ? 1u : 0u) |
+    slot_at(L, st.it & 1)[d] = (uint8_t)sout;
+    chg_at(L, st.it & 1)[d] = (uint8_t)emask;
+    uint32_t ovf = ((nN > hcap || nS > hcap || nW > hcap || nE > hcap) ? 1u : 0u) |
                    ((nev > wcap || runaway) ? 2u : 0u);
-    if (changed) atomicOr(&fl->changed, 1u);
+    if (emask) atomicOr(&fl->changed, 1u);
     if (ovf) atomicOr(&fl->overflow, ovf);
     atomicMax(&fl->fmax, (uint32_t)nbound);
+    atomicAdd(&fl->runs, 1u);
     atomicAdd(&fl->events, (unsigned long long)(nev - nev0));
   }
 }
@@ -868,8 +923,7 @@ __global__ __launch_bounds__(256) void observables_kernel(const int8_t* s, int L
 
 // ------------------------------------------------------------ launchers
 hipError_t launch_relax(const Lattice& L, const Step& st, hipStream_t stream) {
-  size_t lds = (size_t)(L.bx + 2) * (L.by + 2);
-  lds = (lds + 15) & ~(size_t)15;
+  size_t lds = relax_lds_bytes(L.bx, L.by, L.hcap);
   hipLaunchKernelGGL(relax_kernel, dim3(L.nsub), dim3(64), lds, stream, L, st);
   return hipGetLastError();
 }
@@ -896,8 +950,7 @@ hipError_t build_window_graph(const Lattice& L, const Step* dstep, int k, hipGra
   Lattice Lc = L;
   const Step* sp = dstep;
   std::vector<int> idx(k);
-  size_t lds = (size_t)(L.bx + 2) * (L.by + 2);
-  lds = (lds + 15) & ~(size_t)15;
+  size_t lds = relax_lds_bytes(L.bx, L.by, L.hcap);
   for (int i = 0; i < k && e == hipSuccess; ++i) {
     idx[i] = i;
     void* rargs[] = {&Lc, &sp, &idx[i]};
@@ -920,6 +973,8 @@ hipError_t launch_batch(const BatchArgs& B, int waves, size_t lds, hipStream_t s
   hipLaunchKernelGGL(batch_kernel, dim3(waves), dim3(64), lds, stream, B);
   return hipGetLastError();
 }
+
+size_t relax_lds(const Lattice& L) { return relax_lds_bytes(L.bx, L.by, L.hcap); }
 
 int batch_waves_per_cu(size_t lds) {
   int n = 0;
