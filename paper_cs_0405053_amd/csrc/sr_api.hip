@@ -51,6 +51,7 @@ struct sr_sim {
   int64_t relax_launches = 0;
   double relax_ms = 0.0;
   int64_t batch_tasks = 0;
+  unsigned long long* need = nullptr;   // batched form's need bitmaps
   double last_batch_ms = 0.0;
   // captured windows: graph of k iterations, keyed by k (rebuilt when the
   // buffers move); the window descriptor is read from dstep
@@ -190,6 +191,8 @@ static void free_all(sr_sim* s) {
   if (s->obs) (void)hipFree(s->obs);
   if (s->hflags) (void)hipHostFree(s->hflags);
   if (s->init_copy) (void)hipFree(s->init_copy);
+  if (s->need) (void)hipFree(s->need);
+  s->need = nullptr;
   if (s->dstep) (void)hipFree(s->dstep);
   if (s->hstep) (void)hipHostFree(s->hstep);
   s->dstep = nullptr; s->hstep = nullptr;
@@ -280,6 +283,8 @@ static int create_impl(const sr_params* pin, void* stream, sr_sim** out, bool in
   for (auto& e : s->ev)
     if (hipEventCreate(&e) != hipSuccess) return fail(SR_EDEVICE, "cannot create events");
   if (hipMalloc(&s->dstep, sizeof(Step)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate step");
+  if (hipMalloc(&s->need, 2 * (size_t)((L.nsub + 63) / 64) * sizeof(unsigned long long)) != hipSuccess)
+    return fail(SR_ENOMEM, "cannot allocate need bitmaps");
   if (hipHostMalloc(&s->hstep, sizeof(Step), hipHostMallocDefault) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate pinned step");
   {
     const char* ng = std::getenv("SR_NO_GRAPHS");
@@ -676,6 +681,8 @@ extern "C" int sr_batch_run(sr_sim* const* sims, int32_t n, void* stream_) {
   for (int k = 0; k < m; ++k) {
     sr_sim* s = sims[idx[k]];
     lat[k] = s->L;
+    lat[k].need = s->need;
+    HIP_OR_FAIL(s0, hipMemsetAsync(s->need, 0, 2 * (size_t)((s->L.nsub + 63) / 64) * sizeof(unsigned long long), stream));
     LatRun& r = run[k];
     std::memset(&r, 0, sizeof(r));
     r.st = s->st;
@@ -710,6 +717,9 @@ extern "C" int sr_batch_run(sr_sim* const* sims, int32_t n, void* stream_) {
   BatchArgs args;
   args.ctr = dctr; args.q = dq; args.lat = dlat; args.run = drun;
   args.nlat = (uint32_t)m; args.qmask = (uint32_t)(qn - 1);
+  args.take = 1;
+  if (const char* tk = std::getenv("SR_BATCH_TAKE")) args.take = std::max(1, std::min(4, std::atoi(tk)));
+  args.pad = 0;
   hipEvent_t e0 = s0->ev[0], e1 = s0->ev[1];
   int rc = SR_OK;
   if (hipMemcpyAsync(dlat, lat.data(), m * sizeof(Lattice), hipMemcpyHostToDevice, stream) != hipSuccess ||
@@ -719,6 +729,7 @@ extern "C" int sr_batch_run(sr_sim* const* sims, int32_t n, void* stream_) {
       hipEventRecord(e0, stream) != hipSuccess || launch_batch(args, waves, lds, stream) != hipSuccess ||
       hipEventRecord(e1, stream) != hipSuccess ||
       hipMemcpyAsync(run.data(), drun, m * sizeof(LatRun), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipMemcpyAsync(&ctr, dctr, sizeof(ctr), hipMemcpyDeviceToHost, stream) != hipSuccess ||
       hipStreamSynchronize(stream) != hipSuccess) {
     release();
     SR_FAIL(s0, SR_EDEVICE, "persistent batch kernel failed: %s", hipGetErrorString(hipGetLastError()));
@@ -739,7 +750,7 @@ extern "C" int sr_batch_run(sr_sim* const* sims, int32_t n, void* stream_) {
     s->relax_launches += 1;
     s->relax_ms += ms;
     s->batch_tasks += r.tasks;
-    s->runs += r.tasks;
+    s->runs += r.runs;
     int one = SR_OK;
     if (r.status == kOverflow) {
       // grow and finish alone from the last committed window
@@ -750,7 +761,8 @@ extern "C" int sr_batch_run(sr_sim* const* sims, int32_t n, void* stream_) {
       s->err = "window did not converge within max_iters (batched run)";
     } else if (r.status != kDone) {
       one = SR_EDEVICE;
-      s->err = "batched run ended early (status " + std::to_string(r.status) + ")";
+      s->err = "batched run ended early (status " + std::to_string(r.status) +
+               (ctr.abort ? ", the persistent kernel gave up waiting for work)" : ")");
     }
     if (one != SR_OK && rc == SR_OK) {
       rc = one;

@@ -77,6 +77,9 @@ struct Lattice {
   uint32_t* ckn;          // [nsub] valid checkpoints of that run
   int32_t nck;            // checkpoints per subdomain and window
   int32_t ckint;          // events + break points between checkpoints
+  unsigned long long* need;  // batched form: 2 x ceil(nsub/64) bitmaps, by
+                          // iteration parity: subdomains to run in that
+                          // iteration (set by the runs of the one before)
   uint64_t* wlog;         // [nsub][wcap]: tick << 16 | local site
   uint32_t* wcnt;         // [nsub]
   IterFlags* flags;       // [kMaxBatch], one per queued iteration
@@ -104,6 +107,10 @@ __host__ __device__ inline uint8_t* slot_at(const LT& L, int q) { return L.slot 
 template <class LT>
 __host__ __device__ inline uint8_t* chg_at(const LT& L, int q) { return L.chg + (q & 1) * L.nsub; }
 template <class LT>
+__host__ __device__ inline unsigned long long* need_at(const LT& L, int q) {
+  return L.need + (q & 1) * ((L.nsub + 63) / 64);
+}
+template <class LT>
 __host__ __device__ inline int64_t* fct_at(const LT& L, int q) {
   return L.fct + (q & 1) * (L.nsub * kEdges);
 }
@@ -127,9 +134,9 @@ struct LatRun {
   int32_t status;          // kRunning, kDone, kOverflow, kNoConv
   int32_t last_g, last_f;
   uint32_t fmax_win;
-  int64_t windows, iterations, events, tasks;
+  int64_t windows, iterations, events, tasks, runs;
 };
-enum { kRunning = 0, kDone = 1, kOverflow = 2, kNoConv = 3 };
+enum { kRunning = 0, kDone = 1, kOverflow = 2, kNoConv = 3, kBad = 4 };
 
 // Device work queue of (lattice, subdomain) tasks.  A slot holds
 // (ticket + 1) << 32 | lattice << 20 | subdomain; a consumer owning ticket p
@@ -138,7 +145,7 @@ struct BatchCounters {
   unsigned long long head;     // next ticket to hand to a consumer
   unsigned long long tail;     // next ticket to hand to a producer
   uint32_t done;               // lattices finished
-  uint32_t pad;
+  uint32_t abort;              // set when a wave waited far too long
 };
 struct BatchArgs {             // read-only for the kernel's lifetime
   BatchCounters* ctr;
@@ -146,6 +153,8 @@ struct BatchArgs {             // read-only for the kernel's lifetime
   const Lattice* lat;
   LatRun* run;
   uint32_t nlat, qmask;
+  int32_t take;                // tickets a wave may take at once (1..4)
+  int32_t pad;
 };
 
 }  // namespace sr

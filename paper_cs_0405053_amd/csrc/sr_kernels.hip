@@ -643,6 +643,14 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
     uint32_t ovf = ((nN > hcap || nS > hcap || nW > hcap || nE > hcap) ? 1u : 0u) |
                    ((nev > wcap || runaway) ? 2u : 0u);
     if (emask) atomicOr(&fl->changed, 1u);
+    if (L.need && emask) {
+      // batched form: the neighbour facing each changed edge runs next time
+      unsigned long long* nb = need_at(L, (st.it + 1) & 1);
+      const int facing[4] = {dn, ds, dw, de};
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (emask & (1u << e)) atomicOr(&nb[facing[e] >> 6], 1ull << (facing[e] & 63));
+    }
     if (ovf) atomicOr(&fl->overflow, ovf);
     atomicMax(&fl->fmax, (uint32_t)nbound);
     atomicAdd(&fl->runs, 1u);
@@ -753,42 +761,66 @@ __device__ __forceinline__ IterFlags load_flags(const IterFlags* p) {
 }
 
 // Wave-cooperative enqueue of the subdomains of lattice `lat` that run in
-// iteration `it` (all of them when it == 0); the others keep their lists.
-// Sets run.remaining before publishing anything.
-__device__ void enqueue_iteration(const BatchArgs& B, int lat, LatRun* run, CLattice& L, int it,
-                                  int lane) {
+// iteration `it`: all of them when it == 0, else those whose facing input
+// lists changed in iteration it - 1 (their bits in the need bitmap).  The
+// others keep their lists: the slot array is copied forward and the change
+// masks cleared before anything is published.  Sets run.remaining first.
+__device__ uint32_t enqueue_iteration(const BatchArgs& B, int lat, LatRun* run, CLattice& L, int it,
+                                      int lane) {
   const int nsub = L.nsub;
-  uint32_t count = 0;
-  for (int b = 0; b < nsub; b += 64) {
-    int d = b + lane;
-    bool need = d < nsub && (it == 0 || inputs_changed(L, it, d));
-    count += (uint32_t)__popcll(ballot(need));
-    if (d < nsub && !need) {
-      slot_at(L, it & 1)[d] = slot_at(L, (it + 1) & 1)[d];
-      chg_at(L, it & 1)[d] = 0;
-    }
+  const int nw = (nsub + 63) / 64;
+  unsigned long long* nb = need_at(L, it & 1);
+  if (it > 0) {
+    const uint8_t* sp = slot_at(L, (it + 1) & 1);
+    uint8_t* sn = slot_at(L, it & 1);
+    uint8_t* cn = chg_at(L, it & 1);
+    for (int i = lane; i < nsub; i += 64) { sn[i] = sp[i]; cn[i] = 0; }
   }
+  uint32_t count = 0;
+  for (int w = 0; w < nw; w += 64) {
+    unsigned long long m = 0;
+    if (w + lane < nw) {
+      m = it == 0 ? ~0ull : __hip_atomic_load(&nb[w + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (w + lane == nw - 1 && (nsub & 63)) m &= (1ull << (nsub & 63)) - 1;
+    }
+    count += (uint32_t)__popcll(m);
+  }
+  count = (uint32_t)wave_sum64(count);
+  if (count == 0) return 0;                     // caller turns this into an error
   if (lane == 0) {
     run->remaining = (int32_t)count;
     run->tasks += count;
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  for (int b = 0; b < nsub; b += 64) {
-    int d = b + lane;
-    bool need = d < nsub && (it == 0 || inputs_changed(L, it, d));
-    uint64_t m = ballot(need);
-    if (!m) continue;
-    unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(&B.ctr->tail, (unsigned long long)__popcll(m));
-    base = ((uint64_t)rdl((uint32_t)(base >> 32), 0) << 32) | rdl((uint32_t)base, 0);
-    if (need) {
-      uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-      unsigned long long t = base + below;
-      unsigned long long v = ((t + 1) << 32) | ((unsigned long long)lat << 20) | (unsigned)d;
-      __hip_atomic_store(&B.q[t & B.qmask], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  unsigned long long base = 0;
+  if (lane == 0) base = atomicAdd(&B.ctr->tail, (unsigned long long)count);
+  base = ((uint64_t)rdl((uint32_t)(base >> 32), 0) << 32) | rdl((uint32_t)base, 0);
+  // lane-major walk: word w of the bitmap, its set bits in ascending order
+  for (int w0 = 0; w0 < nw; w0 += 64) {
+    unsigned long long m = 0;
+    if (w0 + lane < nw) {
+      m = it == 0 ? ~0ull : __hip_atomic_load(&nb[w0 + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (w0 + lane == nw - 1 && (nsub & 63)) m &= (1ull << (nsub & 63)) - 1;
+      // reused two iterations later, when other XCDs set bits in it with
+      // device-scope atomics: clear it with one too (a plain store could sit
+      // dirty in this XCD's L2 and be written back over their bits)
+      if (it > 0) __hip_atomic_store(&nb[w0 + lane], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    uint32_t c = (uint32_t)__popcll(m);
+    uint32_t excl = wave_incl_scan(c) - c;
+    uint32_t chunk_tot = rdl(wave_incl_scan(c), 63);
+    unsigned long long at = base + excl;
+    while (m) {
+      int bit = ctz64(m);
+      m &= m - 1;
+      int d = (w0 + lane) * 64 + bit;
+      unsigned long long v = ((at + 1) << 32) | ((unsigned long long)lat << 20) | (unsigned)d;
+      __hip_atomic_store(&B.q[at & B.qmask], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      at++;
+    }
+    base += chunk_tot;
   }
+  return count;
 }
 
 // The last task of an iteration of lattice `lat`: compare step (c) of the
@@ -804,6 +836,7 @@ __device__ void decide(const BatchArgs& B, int lat, int lane) {
   if (lane == 0) {
     run->iterations += 1;
     run->events += (int64_t)f.events;
+    run->runs += (int64_t)f.runs;
     run->fmax_win = max(run->fmax_win, f.fmax);
   }
   int next_it = -1;
@@ -846,38 +879,84 @@ __device__ void decide(const BatchArgs& B, int lat, int lane) {
     run->st = st;
     run->fl.changed = 0; run->fl.overflow = 0; run->fl.fmax = 0; run->fl.runs = 0; run->fl.events = 0;
   }
-  enqueue_iteration(B, lat, run, L, next_it, lane);
+  if (enqueue_iteration(B, lat, run, L, next_it, lane) == 0) {
+    // a changed iteration must schedule some subdomain; never wait forever
+    if (lane == 0) run->status = kBad;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (lane == 0) atomicAdd(&B.ctr->done, 1u);
+  }
 }
+
+// Tickets are taken one at a time, or up to kTake at once when that many are
+// already reserved by producers (then none of them can depend on a task this
+// wave holds, and one acquire and one release cover them all: the
+// agent-scope fences write back and invalidate the XCD caches, the costliest
+// step of a short task).
+constexpr int kTake = 4;
+// Empty polls of one queue slot before the kernel gives up (about ten
+// seconds; a task takes microseconds to milliseconds).
+constexpr uint32_t kSpinBudget = 20u << 20;
 
 __global__ __launch_bounds__(64) void batch_kernel(BatchArgs B) {
   extern __shared__ int8_t tile[];
   const int lane = lane_id();
   CLattice* lats = (CLattice*)B.lat;
   for (;;) {
-    unsigned long long t = 0;
-    if (lane == 0) t = atomicAdd(&B.ctr->head, 1ull);
-    t = ((uint64_t)rdl((uint32_t)(t >> 32), 0) << 32) | rdl((uint32_t)t, 0);
-    const uint32_t want = (uint32_t)(t + 1);
-    unsigned long long v;
-    for (;;) {
-      v = __hip_atomic_load(&B.q[t & B.qmask], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if ((uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32)) == want) break;
-      if (__hip_atomic_load(&B.ctr->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= B.nlat) return;
-      __builtin_amdgcn_s_sleep(2);
+    unsigned long long t0 = 0;
+    int k = 1;
+    if (lane == 0) {
+      unsigned long long h = __hip_atomic_load(&B.ctr->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      unsigned long long tl = __hip_atomic_load(&B.ctr->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      bool got = false;
+      if (B.take > 1 && tl > h + 1) {
+        int kk = (tl - h) >= (unsigned long long)B.take ? B.take : (int)(tl - h);
+        unsigned long long seen = atomicCAS(&B.ctr->head, h, h + (unsigned long long)kk);
+        if (seen == h) { t0 = h; k = kk; got = true; }
+      }
+      if (!got) { t0 = atomicAdd(&B.ctr->head, 1ull); k = 1; }
+    }
+    t0 = ((uint64_t)rdl((uint32_t)(t0 >> 32), 0) << 32) | rdl((uint32_t)t0, 0);
+    k = (int)rdl((uint32_t)k, 0);
+    // wait for the k slots; lane i keeps task i
+    uint32_t mine = 0;
+    for (int i = 0; i < k; ++i) {
+      const unsigned long long t = t0 + (unsigned long long)i;
+      const uint32_t want = (uint32_t)(t + 1);
+      unsigned long long v;
+      uint32_t spins = 0;
+      for (;;) {
+        v = __hip_atomic_load(&B.q[t & B.qmask], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32)) == want) break;
+        if (__hip_atomic_load(&B.ctr->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= B.nlat) return;
+        if (__hip_atomic_load(&B.ctr->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+        if (++spins > kSpinBudget) {
+          // far longer than any task takes: give up rather than hang
+          if (lane == 0) __hip_atomic_store(&B.ctr->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          return;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+      if (lane == i) mine = (uint32_t)v;
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    // the task is wave-uniform: keep it (and all that derives from it) scalar
-    const uint32_t pay = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
-    const int lat = (int)((pay >> 20) & 0xFFF);
-    const int d = (int)(pay & 0xFFFFF);
-    LatRun* run = &B.run[lat];
-    const Step st = load_step(&run->st);
-    relax_subdomain(lats[lat], st, d, tile, &run->fl);
+    for (int i = 0; i < k; ++i) {
+      // the task is wave-uniform: keep it (and all that derives from it) scalar
+      const uint32_t pay = rdl(mine, i);
+      const int lat = (int)((pay >> 20) & 0xFFF);
+      const int d = (int)(pay & 0xFFFFF);
+      LatRun* run = &B.run[lat];
+      const Step st = load_step(&run->st);
+      relax_subdomain(lats[lat], st, d, tile, &run->fl);
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    int last = 0;
-    if (lane == 0) last = (atomicSub(&run->remaining, 1) == 1);
-    last = (int)rdl((uint32_t)last, 0);
-    if (last) decide(B, lat, lane);
+    for (int i = 0; i < k; ++i) {
+      const uint32_t pay = rdl(mine, i);
+      const int lat = (int)((pay >> 20) & 0xFFF);
+      int last = 0;
+      if (lane == 0) last = (atomicSub(&B.run[lat].remaining, 1) == 1);
+      last = (int)rdl((uint32_t)last, 0);
+      if (last) decide(B, lat, lane);
+    }
   }
 }
 

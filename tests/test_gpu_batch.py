@@ -62,13 +62,32 @@ def test_batched_equals_plain_and_oracle():
     sr.batch_run(sims)
     for i, (p, s) in enumerate(zip(ps, sims)):
         got = state(s)
-        assert same(got, plain[i]), f"lattice {i} differs from its plain run"
+        if not same(got, plain[i]):
+            names = ["spins", "digests", "flips", "carry", "tick", "windows", "iterations", "total flips"]
+            bad = [n for n, a, b in zip(names, got, plain[i])
+                   if not (np.array_equal(a, b) if isinstance(a, np.ndarray) else a == b)]
+            pp = {k: v for k, v in p.items() if k != "init_spins"}
+            raise AssertionError(f"lattice {i} differs from its plain run in {bad}: {pp}; "
+                                 f"batched {got[4:]} plain {plain[i][4:]}")
     for i in (0, 3, 7):
         ref = oracle.des(ps[i], log=False)
         assert np.array_equal(sims[i].spins(), ref["spins"])
         assert np.array_equal(sims[i].digests()[0], ref["sub_digest"])
     for s in sims:
         s.close()
+
+
+@pytest.mark.parametrize("L,b,win,T", [(32, 16, 1.0, 3.0), (64, 16, 0.5, 2.5), (48, 8, 0.25, 3.5),
+                                       (64, 4, 1.0, 2.0), (32, 8, 0.5, 1.5)])
+def test_single_lattice_batch_equals_plain(L, b, win, T):
+    sr = _sr()
+    p = W.params(L, L, b, b, T=T, h=0.05, window=win, horizon=2.0, seed=31, log_mode="digest")
+    a = sr.Sim(p)
+    a.run()
+    s = sr.Sim(p)
+    sr.batch_run([s])
+    ga, gs = state(a), state(s)
+    assert same(gs, ga), (gs[4:], ga[4:])
 
 
 def test_alone_equals_in_mix():
@@ -100,6 +119,24 @@ def test_batch_resumes_partial_runs_and_reset():
     sr.batch_run(sims)
     for a, b in zip(sims, ref):
         assert same(state(a)[:5], state(b)[:5])
+
+
+def test_batch_repeats_bit_identical():
+    """The same batch three times gives the same bits (the queue order and
+    the XCD a task lands on must not matter)."""
+    sr = _sr()
+    ps = mix(n=16, seed=23, horizon=2.0)
+    ref = None
+    for rep in range(3):
+        sims = [sr.Sim(p) for p in ps]
+        sr.batch_run(sims)
+        got = [state(s) for s in sims]
+        if ref is None:
+            ref = got
+        else:
+            assert all(same(a, b) for a, b in zip(got, ref)), rep
+        for s in sims:
+            s.close()
 
 
 def test_batch_overflow_falls_back_and_matches():
