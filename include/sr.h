@@ -115,7 +115,7 @@ typedef struct sr_sim sr_sim;
 
 /* Create a simulation: validates the parameters, builds the rate table
  * (eqs. pMin / pglauber on the host in IEEE double), allocates the device
- * state and sets the initial spins (Sec. 4: "set to initial states").
+ * state and sets the initial spins (Sec. 4 box, first step).
  * `hip_stream` is a hipStream_t (or NULL).  On success *out owns the handle. */
 int sr_create(const sr_params* p, void* hip_stream, sr_sim** out);
 
@@ -123,8 +123,11 @@ int sr_create(const sr_params* p, void* hip_stream, sr_sim** out);
  * generate / synchronise / compare / synchronise until no history changes,
  * then increment committed time); n_windows < 0 runs to the horizon.  The last
  * window is truncated at the horizon.  iters_out (may be NULL) receives g of
- * each committed window.  *n_done (may be NULL) = windows committed.  On
- * SR_ENOCONV the failing window is left uncommitted and earlier ones stay. */
+ * each committed window and must hold n_windows entries; with n_windows < 0
+ * it must be NULL (SR_EINVAL otherwise), because a tuned step size makes the
+ * number of windows unknown in advance.  *n_done (may be NULL) = windows
+ * committed.  On SR_ENOCONV the failing window is left uncommitted and
+ * earlier ones stay. */
 int sr_run_window(sr_sim* s, int32_t n_windows, int32_t* iters_out, int32_t* n_done);
 
 /* Observables at committed time (eq. hamil parts): M, bond sum, counters. */
@@ -175,11 +178,64 @@ const char* sr_last_error(const sr_sim* s);
  * SR_LOG_DIGEST and the same stream. */
 int sr_batch_run(sr_sim* const* sims, int32_t n, void* hip_stream);
 
-/* ---- tuner ---- choose block and window for a lattice (used when bx = by
- * = 0 or window = 0): block from a fixed table over (L, T, h); window from the
- * step-size rule T_max ~ log N / |dG| of Sec. 5 scaled by a factor learned from
- * measured iterations per window.  Deterministic for given inputs. */
+/* Batched form with a budget: every listed simulation commits at most
+ * max_windows windows (all remaining if max_windows <= 0) in one persistent
+ * launch, then the call returns; later calls continue where each stopped.
+ * This is the scheduling step of continuous batching: between calls,
+ * simulations may be added to or removed from the list. */
+int sr_batch_step(sr_sim* const* sims, int32_t n, int32_t max_windows, void* hip_stream);
+
+/* ---- tuner ---- block and first window for a lattice (used when bx = by =
+ * 0 or window = 0).  Block: a fixed table over (L, T) -- never load-dependent,
+ * because the block partition keys the random streams and so the trajectory.
+ * First window: 4 x the step-size rule T_max = log N / (lambda |dG_i|) of
+ * Sec. 5, clamped to [1/8, 2].  A simulation created with window = 0 then
+ * adapts its step size after every committed window from the measured
+ * iterations g (Sec. 4 box: a step size is chosen at each step), aiming at
+ * about 10 iterations per window; the trajectory does not depend on it. */
 int sr_tune(const sr_params* p, int32_t* bx, int32_t* by, double* window);
+
+/* ---- serving: continuous batching of simulation requests ----
+ * Driven by the caller (no threads).  sr_server_submit queues a request (an
+ * SR_LOG_DIGEST simulation).  Each sr_server_pump is one scheduling round:
+ * admit queued requests in arrival order while their device footprint fits
+ * `hbm_budget` bytes, run one persistent batch step (sr_batch_step) over all
+ * admitted lattices, each committing at most `windows_per_round` windows, and
+ * retire the lattices that reached their horizon (results to sr_server_poll),
+ * which frees memory for the next round.  Requests submitted between rounds
+ * join the next one; their work overlaps on the device with the requests
+ * already running.  A request's result equals its simulation run alone.
+ * Not thread-safe: one thread drives a server. */
+typedef struct sr_server sr_server;
+typedef struct {
+  uint64_t req_id;           /* from sr_server_submit */
+  uint64_t digest;           /* sum of the per-subdomain event digests */
+  int64_t M, bond_sum, flips, events_processed, windows, iterations;
+  double t_arrive, t_start, t_done;  /* seconds since server creation:
+                                        submitted, admitted, retired */
+  int32_t status;            /* SR_OK or an SR_E* code */
+  int32_t bx, by;            /* block the request ran with */
+} sr_result;
+typedef struct {
+  int64_t submitted, completed, failed, queued, rounds;
+  int64_t bytes_in_use, peak_bytes;
+  int32_t peak_active, pad;
+  double busy_s, uptime_s;   /* time inside batch steps / since creation */
+} sr_server_info;
+
+/* hip_stream: stream for all of the server's device work (NULL = default). */
+int sr_server_create(size_t hbm_budget, int32_t windows_per_round, void* hip_stream, sr_server** out);
+/* Copies the parameters (and SR_INIT_USER spins); the arrival time is now.
+ * SR_ENOMEM if the request alone exceeds the budget. */
+int sr_server_submit(sr_server* v, const sr_params* p, uint64_t* req_id);
+/* One round (see above); *n_open (may be NULL) = requests not yet retired. */
+int sr_server_pump(sr_server* v, int32_t* n_open);
+/* Retired requests since the last poll, oldest first; up to cap into the
+ * caller's array, *n = how many. */
+int sr_server_poll(sr_server* v, sr_result* out, int32_t cap, int32_t* n);
+int sr_server_stats(sr_server* v, sr_server_info* out);
+/* Frees every simulation still admitted; queued requests are dropped. */
+void sr_server_destroy(sr_server* v);
 
 #ifdef __cplusplus
 }

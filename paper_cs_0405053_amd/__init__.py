@@ -32,7 +32,9 @@ _LOG = {"digest": 0, "full": 1, 0: 0, 1: 1}
 # every function the C ABI exports (include/sr.h)
 EXPORTS = ["sr_create", "sr_run_window", "sr_observables", "sr_destroy", "sr_get_spins",
            "sr_get_log", "sr_get_digests", "sr_get_carry", "sr_get_rate_table", "sr_save",
-           "sr_load", "sr_last_error", "sr_batch_run", "sr_tune", "sr_reset"]
+           "sr_load", "sr_last_error", "sr_batch_run", "sr_tune", "sr_reset",
+           "sr_batch_step", "sr_server_create", "sr_server_submit", "sr_server_pump",
+           "sr_server_poll", "sr_server_stats", "sr_server_destroy"]
 
 
 class SRError(RuntimeError):
@@ -59,6 +61,21 @@ class Obs(C.Structure):
                 ("window_ticks", C.c_int64), ("horizon_ticks", C.c_int64),
                 ("relax_launches", C.c_int64), ("relax_ms", C.c_double),
                 ("subdomain_runs", C.c_int64)]
+
+
+class Result(C.Structure):
+    _fields_ = [("req_id", C.c_uint64), ("digest", C.c_uint64), ("M", C.c_int64),
+                ("bond_sum", C.c_int64), ("flips", C.c_int64), ("events_processed", C.c_int64),
+                ("windows", C.c_int64), ("iterations", C.c_int64), ("t_arrive", C.c_double),
+                ("t_start", C.c_double), ("t_done", C.c_double), ("status", C.c_int32),
+                ("bx", C.c_int32), ("by", C.c_int32)]
+
+
+class ServerInfo(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("queued", C.c_int64), ("rounds", C.c_int64), ("bytes_in_use", C.c_int64),
+                ("peak_bytes", C.c_int64), ("peak_active", C.c_int32), ("pad", C.c_int32),
+                ("busy_s", C.c_double), ("uptime_s", C.c_double)]
 
 
 _lib = None
@@ -89,6 +106,14 @@ def lib() -> C.CDLL:
         L.sr_last_error.restype = C.c_char_p
         L.sr_batch_run.argtypes = [P, C.c_int32, P]
         L.sr_reset.argtypes = [P]
+        L.sr_batch_step.argtypes = [P, C.c_int32, C.c_int32, P]
+        L.sr_server_create.argtypes = [C.c_size_t, C.c_int32, P, C.POINTER(P)]
+        L.sr_server_submit.argtypes = [P, C.POINTER(Params), C.POINTER(C.c_uint64)]
+        L.sr_server_pump.argtypes = [P, C.POINTER(C.c_int32)]
+        L.sr_server_poll.argtypes = [P, P, C.c_int32, C.POINTER(C.c_int32)]
+        L.sr_server_stats.argtypes = [P, C.POINTER(ServerInfo)]
+        L.sr_server_destroy.argtypes = [P]
+        L.sr_server_destroy.restype = None
         L.sr_tune.argtypes = [C.POINTER(Params), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                               C.POINTER(C.c_double)]
         _lib = L
@@ -187,15 +212,24 @@ class Sim:
     def run(self, n_windows: int = -1) -> np.ndarray:
         """Commit up to n_windows windows (all remaining if < 0); returns the
         iterations g of each committed window."""
-        o = self.observables()
-        left = -(-(o["horizon_ticks"] - o["tick"]) // o["window_ticks"])
-        n = left if n_windows < 0 else min(n_windows, left)
-        g = np.zeros(max(n, 1), dtype=np.int32)
-        done = C.c_int32()
-        rc = lib().sr_run_window(self._h, n_windows, g.ctypes.data_as(C.POINTER(C.c_int32)),
-                                 C.byref(done))
-        self._check(rc, "sr_run_window")
-        return g[:done.value].copy()
+        # The step size may change after every window (tuned windows), so the
+        # number of windows is not known ahead: fetch g in bounded chunks.
+        out = []
+        want = n_windows
+        while want != 0:
+            o = self.observables()
+            if o["tick"] >= o["horizon_ticks"]:
+                break
+            chunk = 256 if want < 0 else min(want, 256)
+            g = np.zeros(chunk, dtype=np.int32)
+            done = C.c_int32()
+            rc = lib().sr_run_window(self._h, chunk, g.ctypes.data_as(C.POINTER(C.c_int32)),
+                                     C.byref(done))
+            out.append(g[:done.value].copy())
+            self._check(rc, "sr_run_window")
+            if want > 0:
+                want -= done.value
+        return np.concatenate(out) if out else np.zeros(0, dtype=np.int32)
 
     def reset(self) -> None:
         """Back to time 0 with the initial spins; keeps all allocations."""
@@ -257,9 +291,74 @@ class Sim:
         return cls(_handle=h)
 
 
+def batch_step(sims: Sequence[Sim], max_windows: int, stream=None) -> None:
+    """Every simulation commits at most max_windows more windows, in one
+    persistent launch (continuous-batching scheduling step)."""
+    arr = (C.c_void_p * len(sims))(*[s.handle for s in sims])
+    rc = lib().sr_batch_step(arr, len(sims), max_windows, _stream_ptr(stream))
+    if rc != SR_OK:
+        raise SRError(rc, "sr_batch_step: " + last_error(sims[0].handle if sims else None))
+
+
 def batch_run(sims: Sequence[Sim], stream=None) -> None:
     """Run every simulation to its horizon in one persistent launch."""
     arr = (C.c_void_p * len(sims))(*[s.handle for s in sims])
     rc = lib().sr_batch_run(arr, len(sims), _stream_ptr(stream))
     if rc != SR_OK:
         raise SRError(rc, "sr_batch_run: " + last_error(sims[0].handle if sims else None))
+
+
+class Server:
+    """Continuous-batching request loop, driven by the caller: `submit`
+    queues a request, every `pump` is one round (admit by HBM footprint, one
+    persistent batch step over all admitted lattices, retire finished ones),
+    `poll` returns retired results."""
+
+    def __init__(self, hbm_budget: int, windows_per_round: int = 8, stream=None):
+        h = C.c_void_p()
+        rc = lib().sr_server_create(int(hbm_budget), int(windows_per_round), _stream_ptr(stream),
+                                    C.byref(h))
+        if rc != SR_OK:
+            raise SRError(rc, last_error(None))
+        self._h = h
+
+    def submit(self, p: Dict) -> int:
+        cp, keep = to_params(dict(p, log_mode="digest"))
+        rid = C.c_uint64()
+        rc = lib().sr_server_submit(self._h, C.byref(cp), C.byref(rid))
+        del keep
+        if rc != SR_OK:
+            raise SRError(rc, last_error(None))
+        return int(rid.value)
+
+    def pump(self) -> int:
+        """One scheduling round; returns the requests not yet retired."""
+        n = C.c_int32()
+        rc = lib().sr_server_pump(self._h, C.byref(n))
+        if rc != SR_OK:
+            raise SRError(rc, "sr_server_pump: " + last_error(None))
+        return int(n.value)
+
+    def poll(self, cap: int = 1024) -> List[Dict]:
+        buf = (Result * cap)()
+        n = C.c_int32()
+        rc = lib().sr_server_poll(self._h, buf, cap, C.byref(n))
+        if rc != SR_OK:
+            raise SRError(rc, "sr_server_poll")
+        return [{k: getattr(buf[i], k) for k, _ in Result._fields_} for i in range(n.value)]
+
+    def stats(self) -> Dict:
+        o = ServerInfo()
+        lib().sr_server_stats(self._h, C.byref(o))
+        return {k: getattr(o, k) for k, _ in ServerInfo._fields_ if k != "pad"}
+
+    def close(self):
+        if self._h is not None:
+            lib().sr_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <deque>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -42,15 +44,18 @@ struct sr_sim {
   Step st;
   hipStream_t stream = nullptr;
   int64_t W = 0, H = 0;             // window and horizon in ticks
+  bool tune = false;                // window chosen by the tuner: adapt it
+  int64_t Wmin = 1, Wmax = 1;       // bounds of the adapted window
   int64_t windows = 0, iterations = 0, events = 0, runs = 0;
   int32_t last_g = 0, last_f = 0;
   unsigned long long* obs = nullptr;   // device scratch for observables
   int8_t* init_copy = nullptr;         // initial spins for sr_reset (SR_INIT_USER)
-  hipEvent_t ev[2 * kMaxBatch] = {};
+  hipEvent_t ev[2] = {};               // brackets the timed device work
   int32_t batch_hint = 8;              // iterations to queue per round trip
   int64_t relax_launches = 0;
   double relax_ms = 0.0;
   int64_t batch_tasks = 0;
+  int failed = SR_OK;                   // last batched run ended in this error
   unsigned long long* need = nullptr;   // batched form's need bitmaps
   double last_batch_ms = 0.0;
   // captured windows: graph of k iterations, keyed by k (rebuilt when the
@@ -204,6 +209,50 @@ static void free_all(sr_sim* s) {
   L.wcnt = nullptr; L.flags = nullptr; s->obs = nullptr; s->hflags = nullptr;
 }
 
+// Buffer capacities of a lattice whose windows are at most Wmax ticks, and
+// the device bytes it will own.  Capacities: every rate is at most lambda =
+// 1, so a window holds at most about (sites x window) events: that plus six
+// standard deviations.  Checkpoints every 8 events or break points, enough
+// for 1.5 x the largest expected count.
+struct Plan {
+  int hcap, wcap, ckint, nck;
+  size_t bytes;
+};
+static Plan plan(const sr_params& p, int64_t Wmax) {
+  Plan pl;
+  double wt = std::ldexp((double)Wmax, -p.tick_bits);
+  double edge = std::max(p.bx, p.by) * wt, blk = (double)p.bx * p.by * wt;
+  pl.hcap = (int)std::max(64.0, std::ceil((edge + 6.0 * std::sqrt(edge) + 16.0) / 64.0) * 64.0);
+  pl.wcap = (int)std::max(64.0, std::ceil((blk + 6.0 * std::sqrt(blk) + 32.0) / 64.0) * 64.0);
+  if (p.hist_cap > 0) pl.hcap = p.hist_cap;
+  if (p.wlog_cap > 0) pl.wcap = p.wlog_cap;
+  pl.ckint = 8;
+  pl.nck = (int)std::min(32.0, std::max(4.0, std::ceil(1.5 * blk / pl.ckint) + 1.0));
+  size_t nsub = (size_t)(p.Lx / p.bx) * (p.Ly / p.by), nsite = (size_t)p.Lx * p.Ly;
+  pl.bytes = 2 * nsite + 2 * nsub * sizeof(Carry) + 2 * nsub * kEdges * (sizeof(uint32_t) + sizeof(int64_t)) +
+             4 * nsub + nsub * pl.nck * sizeof(Ckpt) + 2 * nsub * sizeof(uint32_t) +
+             2 * nsub * kEdges * (size_t)pl.hcap * sizeof(uint64_t) + nsub * (size_t)pl.wcap * sizeof(uint64_t) +
+             2 * ((nsub + 63) / 64) * 8 + (p.init == SR_INIT_USER ? nsite : 0) + 64 * 1024;
+  return pl;
+}
+
+// Parameters after validation and tuning (block, first window); 0 or SR_EINVAL.
+static int resolve(sr_params& p, bool& tuned_window, std::string& why) {
+  if (p.Lx < 4 || p.Ly < 4) { why = "Lx and Ly must be >= 4"; return SR_EINVAL; }
+  if (p.tick_bits == 0) p.tick_bits = 28;
+  if (p.tick_bits < 4 || p.tick_bits > 28) { why = "tick_bits must be in [4, 28]"; return SR_EINVAL; }
+  tuned_window = (p.window == 0.0);
+  if (p.bx == 0 || p.by == 0 || p.window == 0.0) {
+    int32_t tbx, tby; double tw;
+    if (sr_tune(&p, &tbx, &tby, &tw) != SR_OK) { why = "tuner found no block"; return SR_EINVAL; }
+    if (p.bx == 0 || p.by == 0) { p.bx = tbx; p.by = tby; }
+    if (p.window == 0.0) p.window = tw;
+  }
+  if (const char* w = check_block(p.Lx, p.Ly, p.bx, p.by)) { why = w; return SR_EINVAL; }
+  if (!(p.window > 0.0) || !std::isfinite(p.window)) { why = "window must be > 0"; return SR_EINVAL; }
+  return SR_OK;
+}
+
 static int create_impl(const sr_params* pin, void* stream, sr_sim** out, bool init_state) {
   if (!pin || !out) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "null argument");
   *out = nullptr;
@@ -219,6 +268,7 @@ static int create_impl(const sr_params* pin, void* stream, sr_sim** out, bool in
   if (p.init == SR_INIT_USER && !p.init_spins) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "SR_INIT_USER needs init_spins");
   if (p.init != SR_INIT_RANDOM && p.init != SR_INIT_ALL_UP && p.init != SR_INIT_USER)
     SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "unknown init mode");
+  const bool tuned_window = (p.window == 0.0);
   if (p.bx == 0 || p.by == 0 || p.window == 0.0) {
     int32_t tbx, tby; double tw;
     if (sr_tune(&p, &tbx, &tby, &tw) != SR_OK) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "tuner found no block");
@@ -238,6 +288,9 @@ static int create_impl(const sr_params* pin, void* stream, sr_sim** out, bool in
   s->p.init_spins = nullptr;
   s->stream = (hipStream_t)stream;
   s->W = W; s->H = H;
+  s->tune = tuned_window;
+  s->Wmin = std::max<int64_t>(1, to_ticks(1.0 / 64.0, p.tick_bits));
+  s->Wmax = std::max<int64_t>(s->Wmin, to_ticks(4.0, p.tick_bits));
   Lattice& L = s->L;
   std::memset(&L, 0, sizeof(L));
   L.Lx = p.Lx; L.Ly = p.Ly; L.bx = p.bx; L.by = p.by;
@@ -247,18 +300,12 @@ static int create_impl(const sr_params* pin, void* stream, sr_sim** out, bool in
   L.tick_bits = p.tick_bits;
   if (rate_table(p.J, p.h, p.T, p.rule, L.rate) != 0) { delete s; SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "bad rate parameters"); }
   L.seed_lo = (uint32_t)p.seed; L.seed_hi = (uint32_t)(p.seed >> 32);
-  // capacities: at most one flip per site per time unit on average (every
-  // rate <= lambda = 1), plus six standard deviations
-  double wt = std::ldexp((double)W, -p.tick_bits);
-  double edge = std::max(p.bx, p.by) * wt, blk = (double)p.bx * p.by * wt;
-  L.hcap = (int)std::max(64.0, std::ceil((edge + 6.0 * std::sqrt(edge) + 16.0) / 64.0) * 64.0);
-  L.wcap = (int)std::max(64.0, std::ceil((blk + 6.0 * std::sqrt(blk) + 32.0) / 64.0) * 64.0);
-  if (p.hist_cap > 0) L.hcap = p.hist_cap;
-  if (p.wlog_cap > 0) L.wcap = p.wlog_cap;
-  // checkpoints every 8 events or break points, enough for about 1.5x the
-  // largest expected number of events of a window
-  L.ckint = 8;
-  L.nck = (int)std::min(32.0, std::max(4.0, std::ceil(1.5 * blk / L.ckint) + 1.0));
+  if (s->tune) s->Wmax = std::max(s->Wmin, std::min(s->Wmax, 4 * W));
+  const Plan pl = plan(p, s->tune ? s->Wmax : W);
+  L.hcap = pl.hcap;
+  L.wcap = pl.wcap;
+  L.ckint = pl.ckint;
+  L.nck = pl.nck;
 
   size_t nsite = (size_t)p.Lx * p.Ly;
   auto fail = [&](int code, const char* what) {
@@ -444,7 +491,9 @@ static int run_one_window(sr_sim* s, int32_t* g_out) {
         if (g_out) *g_out = g;
         // queue about as many iterations as the last window needed
         s->batch_hint = std::max(2, std::min(kMaxBatch, g + 1));
-        return commit(s);
+        int rc = commit(s);
+        if (s->tune) s->W = tune_window(s->W, g, s->Wmin, s->Wmax);
+        return rc;
       }
     }
     it += k;
@@ -457,6 +506,8 @@ static int run_one_window(sr_sim* s, int32_t* g_out) {
 extern "C" int sr_run_window(sr_sim* s, int32_t n_windows, int32_t* iters_out, int32_t* n_done) {
   if (!s) return SR_EINVAL;
   if (n_done) *n_done = 0;
+  if (n_windows < 0 && iters_out)
+    SR_FAIL(s, SR_EINVAL, "iters_out needs n_windows >= 0 (its size bounds the windows run)");
   int32_t done = 0;
   while (n_windows < 0 || done < n_windows) {
     if (s->st.t_c >= s->H) {
@@ -645,7 +696,13 @@ extern "C" int sr_load(const void* blob, size_t n, void* stream, sr_sim** out) {
 // (only subdomains whose inputs changed) or the next window.  Lattices whose
 // buffers overflowed are finished afterwards by the plain path with larger
 // buffers, from their last committed window.
+extern "C" int sr_batch_step(sr_sim* const* sims, int32_t n, int32_t max_windows, void* stream_);
+
 extern "C" int sr_batch_run(sr_sim* const* sims, int32_t n, void* stream_) {
+  return sr_batch_step(sims, n, -1, stream_);
+}
+
+extern "C" int sr_batch_step(sr_sim* const* sims, int32_t n, int32_t max_windows, void* stream_) {
   if (!sims || n <= 0) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "sr_batch_run needs simulations");
   if (n > 4096) SR_FAIL(sims[0], SR_EINVAL, "at most 4096 lattices per batch");
   hipStream_t stream = (hipStream_t)stream_;
@@ -693,6 +750,9 @@ extern "C" int sr_batch_run(sr_sim* const* sims, int32_t n, void* stream_) {
     r.max_iters = s->p.max_iters;
     r.status = kRunning;
     r.tasks = s->L.nsub;
+    r.tune = s->tune ? 1 : 0;
+    r.win_budget = max_windows > 0 ? max_windows : -1;
+    r.Wmin = s->Wmin; r.Wmax = s->Wmax;
     for (int d = 0; d < s->L.nsub; ++d, ++t)
       q[t] = ((unsigned long long)(t + 1) << 32) | ((unsigned long long)k << 20) | (unsigned)d;
   }
@@ -743,6 +803,7 @@ extern "C" int sr_batch_run(sr_sim* const* sims, int32_t n, void* stream_) {
     const LatRun& r = run[k];
     s->st.t_c = r.st.t_c;
     s->st.wp = r.st.wp;
+    s->W = r.W;
     s->windows += r.windows;
     s->iterations += r.iterations;
     s->events += r.events;
@@ -753,17 +814,18 @@ extern "C" int sr_batch_run(sr_sim* const* sims, int32_t n, void* stream_) {
     s->runs += r.runs;
     int one = SR_OK;
     if (r.status == kOverflow) {
-      // grow and finish alone from the last committed window
+      // grow, then run this step's windows alone from the last committed one
       one = grow(s, 3u);
-      if (one == SR_OK) one = sr_run_window(s, -1, nullptr, nullptr);
+      if (one == SR_OK) one = sr_run_window(s, max_windows > 0 ? max_windows : -1, nullptr, nullptr);
     } else if (r.status == kNoConv) {
       one = SR_ENOCONV;
       s->err = "window did not converge within max_iters (batched run)";
-    } else if (r.status != kDone) {
+    } else if (r.status != kDone && r.status != kPaused) {
       one = SR_EDEVICE;
       s->err = "batched run ended early (status " + std::to_string(r.status) +
                (ctr.abort ? ", the persistent kernel gave up waiting for work)" : ")");
     }
+    s->failed = one;
     if (one != SR_OK && rc == SR_OK) {
       rc = one;
       char b[256];
@@ -774,4 +836,188 @@ extern "C" int sr_batch_run(sr_sim* const* sims, int32_t n, void* stream_) {
   if (rc != SR_OK) for (int k = 0; k < m; ++k) sims[idx[k]]->err = first_err;
   s0->last_batch_ms = ms;
   return rc;
+}
+
+// ------------------------------------------------------------ serving
+// Continuous batching, driven by the caller.  sr_server_submit queues a
+// request; every sr_server_pump is one scheduling round: admit queued
+// requests in arrival order while their device footprint fits the HBM
+// budget, create their simulations, run one budgeted persistent batch step
+// over every admitted lattice (each commits at most `windows_per_round`
+// windows), and retire the lattices that reached their horizon, which frees
+// memory for the next round's admissions.  Requests submitted while a round
+// runs join at the next round.  A lattice's result does not depend on what it
+// shares a round with: the random streams are keyed by the request's own seed
+// and subdomains, and the block comes from the request alone.  All device
+// work happens inside sr_server_pump, on the caller's thread.
+struct sr_server {
+  size_t budget = 0, used = 0, peak_used = 0;
+  int32_t wpr = 8;
+  hipStream_t stream = nullptr;
+  struct Pending {
+    uint64_t id;
+    sr_params p;
+    std::vector<int8_t> spins;
+    double t_arrive;
+    size_t bytes;
+  };
+  struct Active {
+    uint64_t id;
+    sr_sim* s;
+    double t_arrive, t_start;
+    size_t bytes;
+  };
+  std::deque<Pending> pending;
+  std::vector<Active> active;
+  std::deque<sr_result> done;
+  uint64_t next_id = 1;
+  std::chrono::steady_clock::time_point t0;
+  int64_t rounds = 0, completed = 0, failed = 0, submitted = 0;
+  int32_t peak_active = 0;
+  double busy_s = 0.0;
+};
+
+static double server_now(const sr_server* v) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - v->t0).count();
+}
+
+static void server_finish(sr_server* v, sr_server::Active& a, int status) {
+  sr_result r;
+  std::memset(&r, 0, sizeof(r));
+  r.req_id = a.id;
+  r.status = status;
+  r.t_arrive = a.t_arrive;
+  r.t_start = a.t_start;
+  if (status == SR_OK) {
+    sr_obs o;
+    std::vector<uint64_t> dg(a.s->L.nsub);
+    if (sr_observables(a.s, &o) == SR_OK && sr_get_digests(a.s, dg.data(), nullptr) == SR_OK) {
+      for (uint64_t x : dg) r.digest += x;
+      r.M = o.M; r.bond_sum = o.bond_sum; r.flips = o.flips;
+      r.events_processed = o.events_processed;
+      r.windows = o.windows; r.iterations = o.iterations;
+      r.bx = o.bx; r.by = o.by;
+    } else {
+      r.status = SR_EDEVICE;
+    }
+  }
+  sr_destroy(a.s);
+  r.t_done = server_now(v);
+  v->used -= a.bytes;
+  if (r.status == SR_OK) v->completed++; else v->failed++;
+  v->done.push_back(r);
+}
+
+extern "C" int sr_server_create(size_t hbm_budget, int32_t windows_per_round, void* hip_stream,
+                                sr_server** out) {
+  if (!out || hbm_budget == 0) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "sr_server_create needs a budget");
+  sr_server* v = new sr_server();
+  v->budget = hbm_budget;
+  v->wpr = windows_per_round > 0 ? windows_per_round : 8;
+  v->stream = (hipStream_t)hip_stream;
+  v->t0 = std::chrono::steady_clock::now();
+  *out = v;
+  return SR_OK;
+}
+
+extern "C" int sr_server_submit(sr_server* v, const sr_params* pin, uint64_t* req_id) {
+  if (!v || !pin) return SR_EINVAL;
+  sr_params p = *pin;
+  if (p.log_mode != SR_LOG_DIGEST) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "served requests keep digests only");
+  bool tuned = false;
+  std::string why;
+  if (resolve(p, tuned, why) != SR_OK) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "%s", why.c_str());
+  int64_t W = std::max<int64_t>(1, to_ticks(p.window, p.tick_bits));
+  int64_t Wmax = tuned ? std::min(4 * W, to_ticks(4.0, p.tick_bits)) : W;
+  size_t bytes = plan(p, std::max<int64_t>(W, Wmax)).bytes;
+  if (bytes > v->budget) SR_FAIL((sr_sim*)nullptr, SR_ENOMEM, "request needs %zu bytes, more than the budget", bytes);
+  sr_server::Pending q;
+  q.p = *pin;                       // the request as given (tuning redone at creation)
+  if (pin->init == SR_INIT_USER && pin->init_spins)
+    q.spins.assign(pin->init_spins, pin->init_spins + (size_t)pin->Lx * pin->Ly);
+  q.bytes = bytes;
+  q.id = v->next_id++;
+  q.t_arrive = server_now(v);
+  v->submitted++;
+  if (req_id) *req_id = q.id;
+  v->pending.push_back(std::move(q));
+  return SR_OK;
+}
+
+extern "C" int sr_server_pump(sr_server* v, int32_t* n_open) {
+  if (!v) return SR_EINVAL;
+  while (!v->pending.empty() && v->used + v->pending.front().bytes <= v->budget) {
+    sr_server::Pending q = std::move(v->pending.front());
+    v->pending.pop_front();
+    v->used += q.bytes;
+    v->peak_used = std::max(v->peak_used, v->used);
+    sr_params p = q.p;
+    p.init_spins = q.spins.empty() ? nullptr : q.spins.data();
+    sr_server::Active a{q.id, nullptr, q.t_arrive, server_now(v), q.bytes};
+    int rc = sr_create(&p, v->stream, &a.s);
+    if (rc != SR_OK) {
+      sr_result r;
+      std::memset(&r, 0, sizeof(r));
+      r.req_id = q.id; r.status = rc; r.t_arrive = q.t_arrive; r.t_start = a.t_start;
+      r.t_done = server_now(v);
+      v->used -= q.bytes;
+      v->failed++;
+      v->done.push_back(r);
+      continue;
+    }
+    v->active.push_back(a);
+  }
+  int rc = SR_OK;
+  if (!v->active.empty()) {
+    v->peak_active = std::max<int32_t>(v->peak_active, (int32_t)v->active.size());
+    std::vector<sr_sim*> sims;
+    for (auto& a : v->active) sims.push_back(a.s);
+    double tb = server_now(v);
+    rc = sr_batch_step(sims.data(), (int32_t)sims.size(), v->wpr, v->stream);
+    v->busy_s += server_now(v) - tb;
+    v->rounds++;
+    std::vector<sr_server::Active> keep;
+    for (auto& a : v->active) {
+      if (a.s->failed != SR_OK) server_finish(v, a, a.s->failed);
+      else if (rc != SR_OK && rc != SR_ENOCONV) server_finish(v, a, rc);
+      else if (a.s->st.t_c >= a.s->H) server_finish(v, a, SR_OK);
+      else keep.push_back(a);
+    }
+    v->active.swap(keep);
+  }
+  if (n_open) *n_open = (int32_t)(v->active.size() + v->pending.size());
+  return (rc == SR_OK || rc == SR_ENOCONV) ? SR_OK : rc;
+}
+
+extern "C" int sr_server_poll(sr_server* v, sr_result* out, int32_t cap, int32_t* n) {
+  if (!v || !n) return SR_EINVAL;
+  int32_t k = 0;
+  while (k < cap && !v->done.empty()) {
+    out[k++] = v->done.front();
+    v->done.pop_front();
+  }
+  *n = k;
+  return SR_OK;
+}
+
+extern "C" int sr_server_stats(sr_server* v, sr_server_info* o) {
+  if (!v || !o) return SR_EINVAL;
+  std::memset(o, 0, sizeof(*o));
+  o->submitted = v->submitted;
+  o->completed = v->completed;
+  o->failed = v->failed;
+  o->queued = (int64_t)v->pending.size();
+  o->rounds = v->rounds;
+  o->bytes_in_use = (int64_t)v->used;
+  o->peak_bytes = (int64_t)v->peak_used;
+  o->peak_active = v->peak_active;
+  o->busy_s = v->busy_s;
+  o->uptime_s = server_now(v);
+  return SR_OK;
+}
+
+extern "C" void sr_server_destroy(sr_server* v) {
+  if (!v) return;
+  for (auto& a : v->active) sr_destroy(a.s);
+  delete v;
 }

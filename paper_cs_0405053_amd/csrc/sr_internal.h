@@ -135,8 +135,26 @@ struct LatRun {
   int32_t last_g, last_f;
   uint32_t fmax_win;
   int64_t windows, iterations, events, tasks, runs;
+  int32_t tune;            // adapt W after every window (see tune_window)
+  int32_t win_budget;      // windows to commit in this launch (< 0: no limit)
+  int64_t Wmin, Wmax;
 };
-enum { kRunning = 0, kDone = 1, kOverflow = 2, kNoConv = 3, kBad = 4 };
+enum { kRunning = 0, kDone = 1, kOverflow = 2, kNoConv = 3, kBad = 4, kPaused = 5 };
+
+// Step size for the next window (Sec. 4 box: a step size is chosen at every
+// step; the trajectory does not depend on it).  Aims at about kTargetG
+// iterations per window, at most halving or doubling per window.
+constexpr int kTargetG = 10;
+__host__ __device__ inline int64_t tune_window(int64_t W, int g, int64_t Wmin, int64_t Wmax) {
+  if (g < 1) g = 1;
+  int64_t want = (int64_t)((double)W * kTargetG / g);
+  int64_t nw = (W + want) / 2;                 // damped
+  if (nw < W / 2) nw = W / 2;
+  if (nw > 2 * W) nw = 2 * W;
+  if (nw < Wmin) nw = Wmin;
+  if (nw > Wmax) nw = Wmax;
+  return nw < 1 ? 1 : nw;
+}
 
 // Device work queue of (lattice, subdomain) tasks.  A slot holds
 // (ticket + 1) << 32 | lattice << 20 | subdomain; a consumer owning ticket p

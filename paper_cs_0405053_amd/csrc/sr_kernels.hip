@@ -854,17 +854,27 @@ __device__ void decide(const BatchArgs& B, int lat, int lane) {
     // converged: the working outputs become committed (parity flip)
     st.wp ^= 1;
     st.t_c = st.t_end;
+    const int64_t wins = u64s(run->windows) + 1;     // read by every lane before the update
     if (lane == 0) {
-      run->windows += 1;
+      run->windows = wins;
       run->last_g = st.it + 1;
       run->last_f = (int32_t)run->fmax_win;
       run->fmax_win = 0;
     }
+    int64_t W = u64s(run->W);
+    if (run->tune) {
+      W = tune_window(W, st.it + 1, run->Wmin, run->Wmax);
+      if (lane == 0) run->W = W;
+    }
     if (st.t_c >= run->H) {
       if (lane == 0) { run->status = kDone; run->st = st; }
       finish = true;
+    } else if (run->win_budget >= 0 && wins >= run->win_budget) {
+      // this launch's share of windows is done: pause at committed time
+      if (lane == 0) { run->status = kPaused; run->st = st; }
+      finish = true;
     } else {
-      st.t_end = min64(st.t_c + run->W, run->H);
+      st.t_end = min64(st.t_c + W, run->H);
       next_it = 0;
     }
   }

@@ -1,0 +1,157 @@
+// Scenarios for the host runtime under AddressSanitizer (see mock_runtime.cpp).
+// Usage: drive <scenario>; prints "ok <scenario>" and exits 0 on success.
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "../../include/sr.h"
+
+extern "C" size_t sr_mock_live_allocations();
+
+#define CHECK(c)                                                              \
+  do {                                                                        \
+    if (!(c)) {                                                               \
+      std::fprintf(stderr, "check failed at line %d: %s (%s)\n", __LINE__, #c, \
+                   sr_last_error(nullptr));                                   \
+      std::exit(1);                                                           \
+    }                                                                         \
+  } while (0)
+
+static sr_params params(int L, double window, double horizon, uint64_t seed) {
+  sr_params p;
+  std::memset(&p, 0, sizeof(p));
+  p.Lx = p.Ly = L;
+  p.J = 1.0; p.h = 0.1; p.T = 2.0;
+  p.window = window; p.horizon = horizon; p.seed = seed;
+  p.log_mode = SR_LOG_DIGEST;
+  return p;
+}
+
+// A tuned window shrinks when windows need many iterations: more windows are
+// committed than the first window length predicts, and iters_out is bounded
+// by n_windows only.
+static void tuned() {
+  sr_params p = params(128, 0.0, 3.0, 1);
+  sr_sim* s = nullptr;
+  CHECK(sr_create(&p, nullptr, &s) == SR_OK);
+  sr_obs o;
+  CHECK(sr_observables(s, &o) == SR_OK);
+  const long long predicted = (o.horizon_ticks + o.window_ticks - 1) / o.window_ticks;
+  int32_t g[4], done = 0;
+  CHECK(sr_run_window(s, -1, g, &done) == SR_EINVAL);    // unbounded count
+  long long total = 0;
+  for (;;) {
+    int rc = sr_run_window(s, 4, g, &done);
+    if (rc == SR_EDONE) break;
+    CHECK(rc == SR_OK && done >= 1 && done <= 4);
+    for (int i = 0; i < done; ++i) CHECK(g[i] == std::atoi(std::getenv("SR_MOCK_G")));
+    total += done;
+  }
+  CHECK(sr_observables(s, &o) == SR_OK);
+  CHECK(o.tick == o.horizon_ticks && o.windows == total);
+  CHECK(total > predicted);
+  CHECK(sr_run_window(s, -1, nullptr, &done) == SR_OK && done == 0);
+  sr_destroy(s);
+  std::printf("windows %lld, first-window estimate %lld\n", total, predicted);
+}
+
+// Requests arrive between rounds, are admitted by footprint and retired;
+// afterwards plain simulations are created, run and destroyed again.
+static void server() {
+  sr_server* v = nullptr;
+  CHECK(sr_server_create((size_t)64 << 20, 3, nullptr, &v) == SR_OK);
+  std::vector<uint64_t> ids;
+  int32_t open = 0;
+  for (int i = 0; i < 10; ++i) {
+    sr_params p = params(64 + 16 * (i % 9), 0.0, 0.5 + 0.3 * i, 7000 + i);
+    uint64_t id = 0;
+    CHECK(sr_server_submit(v, &p, &id) == SR_OK);
+    ids.push_back(id);
+    CHECK(sr_server_pump(v, &open) == SR_OK);
+  }
+  sr_params big = params(4096, 0.0, 5.0, 1);
+  uint64_t id = 0;
+  CHECK(sr_server_submit(v, &big, &id) == SR_ENOMEM);
+  for (int r = 0; open && r < 10000; ++r) CHECK(sr_server_pump(v, &open) == SR_OK);
+  CHECK(open == 0);
+  sr_result res[16];
+  int32_t n = 0;
+  CHECK(sr_server_poll(v, res, 16, &n) == SR_OK && n == 10);
+  for (int i = 0; i < n; ++i) CHECK(res[i].status == SR_OK && res[i].t_done >= res[i].t_start);
+  sr_server_info info;
+  CHECK(sr_server_stats(v, &info) == SR_OK);
+  CHECK(info.completed == 10 && info.failed == 0 && info.bytes_in_use == 0);
+  CHECK(info.peak_bytes <= (int64_t)(64 << 20));
+  sr_server_destroy(v);
+  for (int i = 0; i < 10; ++i) {
+    sr_params p = params(64 + 16 * (i % 9), 0.0, 0.5 + 0.3 * i, 7000 + i);
+    sr_sim* s = nullptr;
+    CHECK(sr_create(&p, nullptr, &s) == SR_OK);
+    int32_t done = 0;
+    CHECK(sr_run_window(s, -1, nullptr, &done) == SR_OK && done > 0);
+    sr_destroy(s);
+  }
+}
+
+// Budgeted batch steps, resumption, and the overflow fallback to the plain
+// path (buffers grown, the window re-run from its committed state).
+static void batch() {
+  std::vector<sr_sim*> sims;
+  for (int i = 0; i < 5; ++i) {
+    sr_params p = params(32 + 16 * i, i % 2 ? 0.0 : 0.5, 2.0 + i, 100 + i);
+    sr_sim* s = nullptr;
+    CHECK(sr_create(&p, nullptr, &s) == SR_OK);
+    sims.push_back(s);
+  }
+  CHECK(sr_batch_step(sims.data(), 5, 2, nullptr) == SR_OK);
+  sr_obs o;
+  for (sr_sim* s : sims) CHECK(sr_observables(s, &o) == SR_OK && o.windows <= 2 && o.windows >= 1);
+  CHECK(sr_batch_run(sims.data(), 5, nullptr) == SR_OK);
+  for (sr_sim* s : sims) CHECK(sr_observables(s, &o) == SR_OK && o.tick == o.horizon_ticks);
+  for (sr_sim* s : sims) CHECK(sr_reset(s) == SR_OK);
+  CHECK(sr_batch_run(sims.data(), 5, nullptr) == SR_OK);
+  for (sr_sim* s : sims) CHECK(sr_observables(s, &o) == SR_OK && o.tick == o.horizon_ticks);
+  for (sr_sim* s : sims) sr_destroy(s);
+}
+
+// Save / load round trip and argument errors.
+static void errors() {
+  sr_params p = params(64, 0.5, 2.0, 5);
+  sr_sim* s = nullptr;
+  CHECK(sr_create(&p, nullptr, &s) == SR_OK);
+  CHECK(sr_run_window(s, 2, nullptr, nullptr) == SR_OK);
+  size_t n = 0;
+  CHECK(sr_save(s, nullptr, 0, &n) == SR_OK && n > 0);
+  std::vector<char> blob(n);
+  CHECK(sr_save(s, blob.data(), n, &n) == SR_OK);
+  CHECK(sr_save(s, blob.data(), n - 1, &n) == SR_EINVAL);
+  sr_sim* t = nullptr;
+  CHECK(sr_load(blob.data(), blob.size(), nullptr, &t) == SR_OK);
+  CHECK(sr_load(blob.data(), 16, nullptr, &t) == SR_EINVAL);
+  sr_obs a, b;
+  CHECK(sr_observables(s, &a) == SR_OK && sr_observables(t, &b) == SR_OK);
+  CHECK(a.tick == b.tick && a.windows == b.windows && a.M == b.M);
+  sr_destroy(t);
+  sr_params bad = p;
+  bad.bx = 3; bad.by = 3;
+  CHECK(sr_create(&bad, nullptr, &t) == SR_EINVAL);
+  bad = p;
+  bad.T = 0.0;
+  CHECK(sr_create(&bad, nullptr, &t) == SR_EINVAL);
+  sr_batch_run(&s, 1, nullptr);
+  sr_destroy(s);
+}
+
+int main(int argc, char** argv) {
+  if (argc < 2) return 2;
+  const char* w = argv[1];
+  if (!std::strcmp(w, "tuned")) tuned();
+  else if (!std::strcmp(w, "server")) server();
+  else if (!std::strcmp(w, "batch")) batch();
+  else if (!std::strcmp(w, "errors")) errors();
+  else return 2;
+  CHECK(sr_mock_live_allocations() == 0);
+  std::printf("ok %s\n", w);
+  return 0;
+}

@@ -1,0 +1,142 @@
+// Host-only stand-ins for the HIP runtime and for the library's kernel
+// launchers, so that the host runtime (sr_api.hip) can be exercised under
+// AddressSanitizer without a GPU.  Device memory is host memory; every
+// allocation is tracked and a bad free aborts.  The "kernels" do no physics:
+//   relaxation  -- a window converges after SR_MOCK_G iterations (default 1);
+//   batch       -- every lattice commits windows of its current length, with
+//                  the same step-size rule and window budget as the device
+//                  decider; SR_MOCK_OVERFLOW=1 makes lattice 0 report a
+//                  buffer overflow so that the plain fallback runs.
+#include "hip/hip_runtime.h"
+
+#include <cstdio>
+#include <set>
+
+#include "../../paper_cs_0405053_amd/csrc/sr_internal.h"
+
+static std::set<void*> g_dev, g_host, g_ev;
+
+static int env_int(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  return v ? std::atoi(v) : dflt;
+}
+
+hipError_t hipMalloc(void** p, size_t n) {
+  *p = std::calloc(1, n ? n : 1);
+  g_dev.insert(*p);
+  return hipSuccess;
+}
+hipError_t hipFree(void* p) {
+  if (!g_dev.erase(p)) { std::fprintf(stderr, "hipFree of unknown pointer %p\n", p); std::abort(); }
+  std::free(p);
+  return hipSuccess;
+}
+hipError_t hipHostMalloc(void** p, size_t n, unsigned) {
+  *p = std::calloc(1, n ? n : 1);
+  g_host.insert(*p);
+  return hipSuccess;
+}
+hipError_t hipHostFree(void* p) {
+  if (!g_host.erase(p)) { std::fprintf(stderr, "hipHostFree of unknown pointer %p\n", p); std::abort(); }
+  std::free(p);
+  return hipSuccess;
+}
+hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind, hipStream_t) {
+  std::memcpy(d, s, n);
+  return hipSuccess;
+}
+hipError_t hipMemsetAsync(void* d, int v, size_t n, hipStream_t) {
+  std::memset(d, v, n);
+  return hipSuccess;
+}
+hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+hipError_t hipDeviceSynchronize() { return hipSuccess; }
+hipError_t hipEventCreate(hipEvent_t* e) {
+  *e = (hipEvent_t)std::malloc(8);
+  g_ev.insert(*e);
+  return hipSuccess;
+}
+hipError_t hipEventDestroy(hipEvent_t e) {
+  if (!g_ev.erase(e)) { std::fprintf(stderr, "hipEventDestroy of unknown event\n"); std::abort(); }
+  std::free(e);
+  return hipSuccess;
+}
+hipError_t hipEventRecord(hipEvent_t, hipStream_t) { return hipSuccess; }
+hipError_t hipEventElapsedTime(float* ms, hipEvent_t, hipEvent_t) { *ms = 0.01f; return hipSuccess; }
+const char* hipGetErrorString(hipError_t) { return "host stand-in error"; }
+hipError_t hipGetLastError() { return hipSuccess; }
+hipError_t hipGetDevice(int* d) { *d = 0; return hipSuccess; }
+hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t, int) { *v = 256; return hipSuccess; }
+
+// A "graph" of k relaxation iterations: remembers where the flags and the
+// window descriptor live, as the captured kernels do.
+struct ihipGraphExec_t {
+  sr::IterFlags* flags;
+  const sr::Step* dstep;
+  int k, nsub;
+};
+static void relax_flags(sr::IterFlags* f, int it, int nsub) {
+  std::memset(f, 0, sizeof(*f));
+  f->changed = it < env_int("SR_MOCK_G", 1) - 1;
+  f->runs = (uint32_t)nsub;
+}
+hipError_t hipGraphLaunch(hipGraphExec_t g, hipStream_t) {
+  for (int i = 0; i < g->k; ++i) relax_flags(&g->flags[i], g->dstep->it + i, g->nsub);
+  return hipSuccess;
+}
+hipError_t hipGraphExecDestroy(hipGraphExec_t g) {
+  delete g;
+  return hipSuccess;
+}
+
+extern "C" size_t sr_mock_live_allocations() { return g_dev.size() + g_host.size() + g_ev.size(); }
+
+namespace sr {
+hipError_t launch_relax(const Lattice& L, const Step& st, hipStream_t) {
+  relax_flags(&L.flags[st.fi], st.it, L.nsub);
+  return hipSuccess;
+}
+hipError_t launch_init_random(int8_t* s, int64_t n, uint64_t seed, hipStream_t) {
+  for (int64_t i = 0; i < n; ++i) s[i] = ((seed + (uint64_t)i) & 1) ? 1 : -1;
+  return hipSuccess;
+}
+hipError_t launch_fill(int8_t* s, int64_t n, int8_t v, hipStream_t) {
+  std::memset(s, (unsigned char)v, (size_t)n);
+  return hipSuccess;
+}
+hipError_t launch_observables(const int8_t* s, int Lx, int Ly, unsigned long long* out, hipStream_t) {
+  long long m = 0;
+  for (int64_t i = 0; i < (int64_t)Lx * Ly; ++i) m += s[i];
+  out[0] = (unsigned long long)m;
+  out[1] = 0;
+  return hipSuccess;
+}
+hipError_t launch_batch(const BatchArgs& B, int, size_t, hipStream_t) {
+  const int G = env_int("SR_MOCK_G", 1);
+  for (uint32_t k = 0; k < B.nlat; ++k) {
+    LatRun& r = B.run[k];
+    if (k == 0 && env_int("SR_MOCK_OVERFLOW", 0)) { r.status = kOverflow; continue; }
+    int budget = r.win_budget;
+    r.status = kRunning;
+    while (r.status == kRunning) {
+      r.st.t_c = r.st.t_end;
+      r.st.wp ^= 1;
+      r.windows++;
+      r.iterations += G;
+      r.last_g = G;
+      if (r.tune) r.W = tune_window(r.W, G, r.Wmin, r.Wmax);
+      if (r.st.t_c >= r.H) { r.status = kDone; break; }
+      r.st.t_end = r.st.t_c + r.W < r.H ? r.st.t_c + r.W : r.H;
+      if (budget > 0 && --budget == 0) r.status = kPaused;
+    }
+    B.ctr->done++;
+  }
+  return hipSuccess;
+}
+int batch_waves_per_cu(size_t) { return 4; }
+size_t relax_lds(const Lattice& L) { return 1024 + 64 * (size_t)L.hcap; }
+hipError_t build_window_graph(const Lattice& L, const Step* dstep, int k, hipGraphExec_t* out) {
+  *out = new ihipGraphExec_t{L.flags, dstep, k, L.nsub};
+  return hipSuccess;
+}
+}  // namespace sr
