@@ -48,6 +48,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-medium", action="store_true",
+                    help="skip the headline leg (profiling the other legs alone)")
+    ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--temps", default=None, help="comma list, default all three")
     ap.add_argument("--horizon", type=float, default=100.0,
                     help="shorter horizons only for profiler runs")
@@ -69,6 +73,14 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.no_medium:
+        side = {}
+        if not args.no_batch:
+            side["batched_vs_plain"] = bench_batch(sr, W, stream, torch)
+        if not args.no_serve:
+            side["serving"] = bench_serve(sr, W, stream, n=args.serve_requests)
+        print(json.dumps(side), flush=True)
+        return
     temps = W.MEDIUM_TEMPS if not args.temps else tuple(float(x) for x in args.temps.split(","))
     ps = [W.medium(T=T, horizon=args.horizon) for T in temps]
     sims = [sr.Sim(dict(p, log_mode="digest"), stream=stream) for p in ps]
@@ -185,6 +197,11 @@ def main():
             line["batched_vs_plain"] = bench_batch(sr, W, stream, torch)
         except Exception as e:   # reported, never hidden
             line["batched_vs_plain"] = {"error": repr(e)}
+    if not args.no_serve:
+        try:
+            line["serving"] = bench_serve(sr, W, stream, n=args.serve_requests)
+        except Exception as e:
+            line["serving"] = {"error": repr(e)}
 
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(sr, W, stream, temps)
@@ -238,6 +255,63 @@ def bench_batch(sr, W, stream, torch, n=512, horizon=50.0):
             "plain_flips_per_s": round(flips / t_plain, 1),
             "batched_flips_per_s": round(flips_b / t_batch, 1),
             "speedup": round(t_plain / t_batch, 3), "bit_exact": bool(same and flips == flips_b)}
+
+
+def bench_serve(sr, W, stream, n=64, rate=200.0, budget_gib=96, wpr=8, n_check=3):
+    """Continuous batching under a Poisson request stream: a request is
+    submitted once its arrival time has passed, every pump is one scheduling
+    round (admission by device footprint, one budgeted persistent step over
+    all admitted lattices, retirement).  Latency = completion - nominal
+    arrival, on the server's clock."""
+    import numpy as np
+    reqs = W.serve_stream(n=n, rate=rate)
+    srv = sr.Server(hbm_budget=budget_gib << 30, windows_per_round=wpr, stream=stream)
+    t0 = time.perf_counter()            # the server's clock starts at creation
+    got, ids, nxt = {}, {}, 0
+    while len(got) < n:
+        now = time.perf_counter() - t0
+        while nxt < n and reqs[nxt]["t_arrive"] <= now:
+            p = {k: v for k, v in reqs[nxt].items() if k not in ("t_arrive", "req_id")}
+            ids[srv.submit(p)] = nxt
+            nxt += 1
+        if srv.pump() == 0 and nxt < n:
+            time.sleep(max(0.0, min(0.01, reqs[nxt]["t_arrive"] - (time.perf_counter() - t0))))
+        for r in srv.poll():
+            got[ids[r["req_id"]]] = r
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    bad = [i for i, r in got.items() if r["status"] != 0]
+    lat = np.array([got[i]["t_done"] - reqs[i]["t_arrive"] for i in range(n)])
+    svc = np.array([got[i]["t_done"] - got[i]["t_start"] for i in range(n)])
+    flips = sum(int(r["flips"]) for r in got.values())
+    # a few requests again, alone, on the plain path: must equal their in-mix result
+    small = sorted(range(n), key=lambda i: reqs[i]["Lx"] * reqs[i]["horizon"])[:n_check]
+    same = True
+    for i in small:
+        p = {k: v for k, v in reqs[i].items() if k not in ("t_arrive", "req_id")}
+        s = sr.Sim(p, stream=stream)
+        s.run()
+        o = s.observables()
+        d = int(np.sum(s.digests()[0], dtype=np.uint64))
+        s.close()
+        same &= (d, o["flips"], o["M"]) == (got[i]["digest"], got[i]["flips"], got[i]["M"])
+    last_arrival = reqs[-1]["t_arrive"]
+    return {"workload": f"{n} requests, Poisson arrivals at {rate:g} req/s, L log-uniform in "
+                        "[64,2048] (multiple of 16), T~U[1,3.5], h~U[-0.2,0.2], horizon~U[10,100], "
+                        f"tuned block/window, HBM budget {budget_gib} GiB, {wpr} windows per round",
+            "requests": n, "failed": len(bad),
+            "offered_req_per_s": round(n / max(last_arrival, 1e-9), 1),
+            "served_req_per_s": round(n / wall, 2),
+            "stable": bool(n / wall >= 0.9 * n / max(last_arrival, 1e-9)),
+            "committed_flips_per_s": round(flips / wall, 1),
+            "latency_p50_s": round(float(np.percentile(lat, 50)), 3),
+            "latency_p99_s": round(float(np.percentile(lat, 99)), 3),
+            "service_p50_s": round(float(np.percentile(svc, 50)), 3),
+            "rounds": st["rounds"], "peak_active": st["peak_active"],
+            "peak_gib": round(st["peak_bytes"] / 2**30, 2), "wall_s": round(wall, 2),
+            "gpu_busy_frac": round(st["busy_s"] / max(wall, 1e-9), 3),
+            "alone_equals_in_mix": bool(same), "alone_checked": n_check}
 
 
 def cpu_baseline(sr, W, stream, temps, horizon=1.0):
