@@ -82,7 +82,8 @@ typedef struct {
   int32_t tick_bits;         /* 0 = 28; 4..28 */
   int32_t hist_cap;          /* initial entries per boundary list and window
                                 (0 = sized from the window; grown and the
-                                window re-run on overflow) */
+                                window re-run on overflow; at most 1024,
+                                SR_EINVAL above) */
   int32_t wlog_cap;          /* initial events per subdomain and window
                                 (0 = sized from the window; grown likewise) */
 } sr_params;
@@ -97,7 +98,7 @@ typedef struct {
   int64_t iterations;        /* relaxation iterations so far */
   int32_t last_g;            /* iterations of the last committed window */
   int32_t last_f;            /* max boundary-site events of one subdomain in
-                                one iteration of the last window (Sec. 6 f) */
+                                the last committed window (Sec. 6 f) */
   int32_t tick_bits;
   int32_t n_sub;             /* number of subdomains */
   int32_t bx, by;            /* block in use */

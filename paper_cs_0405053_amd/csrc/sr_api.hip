@@ -46,8 +46,9 @@ struct sr_sim {
   int64_t W = 0, H = 0;             // window and horizon in ticks
   bool tune = false;                // window chosen by the tuner: adapt it
   int64_t Wmin = 1, Wmax = 1;       // bounds of the adapted window
-  int64_t windows = 0, iterations = 0, events = 0, runs = 0;
-  int32_t last_g = 0, last_f = 0;
+  int64_t windows = 0, iterations = 0;
+  int64_t events_base = 0, runs_base = 0;  // work done before a checkpoint load
+  int32_t last_g = 0;
   unsigned long long* obs = nullptr;   // device scratch for observables
   int8_t* init_copy = nullptr;         // initial spins for sr_reset (SR_INIT_USER)
   hipEvent_t ev[2] = {};               // brackets the timed device work
@@ -187,6 +188,8 @@ static void free_all(sr_sim* s) {
   if (L.slot) (void)hipFree(L.slot);
   if (L.chg) (void)hipFree(L.chg);
   if (L.fct) (void)hipFree(L.fct);
+  if (L.stat) (void)hipFree(L.stat);
+  L.stat = nullptr;
   if (L.ck) (void)hipFree(L.ck);
   if (L.ckn) (void)hipFree(L.ckn);
   L.spins = nullptr; L.carry = nullptr; L.hcnt = nullptr; L.slot = nullptr; L.chg = nullptr;
@@ -222,7 +225,8 @@ static Plan plan(const sr_params& p, int64_t Wmax) {
   Plan pl;
   double wt = std::ldexp((double)Wmax, -p.tick_bits);
   double edge = std::max(p.bx, p.by) * wt, blk = (double)p.bx * p.by * wt;
-  pl.hcap = (int)std::max(64.0, std::ceil((edge + 6.0 * std::sqrt(edge) + 16.0) / 64.0) * 64.0);
+  pl.hcap = (int)std::min((double)kMaxHistCap,
+                          std::max(64.0, std::ceil((edge + 6.0 * std::sqrt(edge) + 16.0) / 64.0) * 64.0));
   pl.wcap = (int)std::max(64.0, std::ceil((blk + 6.0 * std::sqrt(blk) + 32.0) / 64.0) * 64.0);
   if (p.hist_cap > 0) pl.hcap = p.hist_cap;
   if (p.wlog_cap > 0) pl.wcap = p.wlog_cap;
@@ -232,7 +236,8 @@ static Plan plan(const sr_params& p, int64_t Wmax) {
   pl.bytes = 2 * nsite + 2 * nsub * sizeof(Carry) + 2 * nsub * kEdges * (sizeof(uint32_t) + sizeof(int64_t)) +
              4 * nsub + nsub * pl.nck * sizeof(Ckpt) + 2 * nsub * sizeof(uint32_t) +
              2 * nsub * kEdges * (size_t)pl.hcap * sizeof(uint64_t) + nsub * (size_t)pl.wcap * sizeof(uint64_t) +
-             2 * ((nsub + 63) / 64) * 8 + (p.init == SR_INIT_USER ? nsite : 0) + 64 * 1024;
+             2 * ((nsub + 63) / 64) * 8 + nsub * sizeof(SubStat) + (p.init == SR_INIT_USER ? nsite : 0) +
+             64 * 1024;
   return pl;
 }
 
@@ -282,6 +287,8 @@ static int create_impl(const sr_params* pin, void* stream, sr_sim** out, bool in
   if (H >= ((int64_t)1 << 46)) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "horizon too long for the tick grid");
   if (p.max_iters <= 0) p.max_iters = 10000;
   if (p.hist_cap < 0 || p.wlog_cap < 0) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "capacities must be >= 0");
+  if (p.hist_cap > kMaxHistCap)   // a relaxation wave keeps 12 lists of this length in LDS
+    SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "hist_cap must be <= %d", kMaxHistCap);
 
   sr_sim* s = new sr_sim();
   s->p = p;
@@ -322,6 +329,9 @@ static int create_impl(const sr_params* pin, void* stream, sr_sim** out, bool in
   if (hipMalloc(&L.fct, 2 * (size_t)L.nsub * kEdges * sizeof(int64_t)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate change ticks");
   if (hipMalloc(&L.ck, (size_t)L.nsub * L.nck * sizeof(Ckpt)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate checkpoints");
   if (hipMalloc(&L.ckn, (size_t)L.nsub * sizeof(uint32_t)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate checkpoint counts");
+  if (hipMalloc(&L.stat, (size_t)L.nsub * sizeof(SubStat)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate work counters");
+  if (hipMemsetAsync(L.stat, 0, (size_t)L.nsub * sizeof(SubStat), s->stream) != hipSuccess)
+    return fail(SR_EDEVICE, "work counter init failed");
   if (hipMalloc(&L.wcnt, (size_t)L.nsub * sizeof(uint32_t)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate log counts");
   if (hipMalloc(&L.flags, kMaxBatch * sizeof(IterFlags)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate flags");
   if (hipMalloc(&s->obs, 4 * sizeof(unsigned long long)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate scratch");
@@ -385,8 +395,8 @@ extern "C" const char* sr_last_error(const sr_sim* s) {
 static int grow(sr_sim* s, uint32_t ovf) {
   Lattice& L = s->L;
   if (ovf & 1u) {
-    if (L.hcap >= 1024) SR_FAIL(s, SR_EOVERFLOW, "boundary list capacity limit reached");
-    L.hcap *= 2;
+    if (L.hcap >= kMaxHistCap) SR_FAIL(s, SR_EOVERFLOW, "boundary list capacity limit reached");
+    L.hcap = std::min(2 * L.hcap, kMaxHistCap);
   }
   if (ovf & 2u) {
     if (L.wcap >= (1 << 22)) SR_FAIL(s, SR_EOVERFLOW, "window log capacity limit reached");
@@ -428,7 +438,6 @@ static int commit(sr_sim* s) {
 static int run_one_window(sr_sim* s, int32_t* g_out) {
   Lattice& L = s->L;
   s->st.t_end = std::min(s->st.t_c + s->W, s->H);
-  uint32_t fmax = 0;
   int it = 0;
   // power-of-two batch sizes, so that few graphs cover every window
   int K = 2;
@@ -474,20 +483,15 @@ static int run_one_window(sr_sim* s, int32_t* g_out) {
     for (int i = 0; i < k; ++i) {
       const IterFlags& f = s->hflags[i];
       s->iterations++;
-      s->events += (int64_t)f.events;
-      s->runs += f.runs;
-      if (f.overflow) {
-        int rc = grow(s, f.overflow);
+      if (f.ovf_hist || f.ovf_log) {
+        int rc = grow(s, (f.ovf_hist ? 1u : 0u) | (f.ovf_log ? 2u : 0u));
         if (rc != SR_OK) return rc;
         it = -k;                   // re-run the window from its committed state
-        fmax = 0;
         break;
       }
-      fmax = std::max(fmax, f.fmax);
       if (!f.changed) {
         int g = it + i + 1;
         s->last_g = g;
-        s->last_f = (int32_t)fmax;
         if (g_out) *g_out = g;
         // queue about as many iterations as the last window needed
         s->batch_hint = std::max(2, std::min(kMaxBatch, g + 1));
@@ -533,18 +537,29 @@ extern "C" int sr_observables(sr_sim* s, sr_obs* o) {
   HIP_OR_FAIL(s, launch_observables(spins_at(L, s->st.wp), L.Lx, L.Ly, s->obs, s->stream));
   HIP_OR_FAIL(s, hipMemcpyAsync(h, s->obs, sizeof(h), hipMemcpyDeviceToHost, s->stream));
   std::vector<Carry> c(L.nsub);
+  std::vector<SubStat> w(L.nsub);
   HIP_OR_FAIL(s, hipMemcpyAsync(c.data(), carry_at(L, s->st.wp), c.size() * sizeof(Carry), hipMemcpyDeviceToHost, s->stream));
+  HIP_OR_FAIL(s, hipMemcpyAsync(w.data(), L.stat, w.size() * sizeof(SubStat), hipMemcpyDeviceToHost, s->stream));
   HIP_OR_FAIL(s, hipStreamSynchronize(s->stream));
   std::memset(o, 0, sizeof(*o));
   o->tick = s->st.t_c;
   o->M = (int64_t)h[0];
   o->bond_sum = (int64_t)h[1];
-  for (const Carry& x : c) o->flips += x.flips;
-  o->events_processed = s->events;
+  int64_t fmax = 0;
+  for (const Carry& x : c) {
+    o->flips += x.flips;
+    fmax = std::max(fmax, x.nbound);
+  }
+  o->events_processed = s->events_base;
+  o->subdomain_runs = s->runs_base;
+  for (const SubStat& x : w) {
+    o->events_processed += (int64_t)x.events;
+    o->subdomain_runs += (int64_t)x.runs;
+  }
   o->windows = s->windows;
   o->iterations = s->iterations;
   o->last_g = s->last_g;
-  o->last_f = s->last_f;
+  o->last_f = s->windows > 0 ? (int32_t)fmax : 0;
   o->tick_bits = s->p.tick_bits;
   o->n_sub = L.nsub;
   o->bx = L.bx; o->by = L.by;
@@ -553,7 +568,6 @@ extern "C" int sr_observables(sr_sim* s, sr_obs* o) {
   o->horizon_ticks = s->H;
   o->relax_launches = s->relax_launches;
   o->relax_ms = s->relax_ms;
-  o->subdomain_runs = s->runs;
   return SR_OK;
 }
 
@@ -566,13 +580,14 @@ extern "C" int sr_reset(sr_sim* s) {
   else if (s->init_copy) HIP_OR_FAIL(s, hipMemcpyAsync(spins_at(L, 0), s->init_copy, (size_t)nsite, hipMemcpyDeviceToDevice, s->stream));
   else SR_FAIL(s, SR_EINVAL, "no initial spins kept (simulation was loaded from a checkpoint)");
   HIP_OR_FAIL(s, hipMemsetAsync(carry_at(L, 0), 0, (size_t)L.nsub * sizeof(Carry), s->stream));
+  HIP_OR_FAIL(s, hipMemsetAsync(L.stat, 0, (size_t)L.nsub * sizeof(SubStat), s->stream));
   HIP_OR_FAIL(s, hipStreamSynchronize(s->stream));
   s->st.t_c = 0; s->st.t_end = 0; s->st.wp = 0; s->st.it = 0;
-  s->windows = s->iterations = s->events = 0;
-  s->last_g = s->last_f = 0;
+  s->windows = s->iterations = 0;
+  s->events_base = s->runs_base = 0;
+  s->last_g = 0;
   s->relax_launches = 0;
   s->relax_ms = 0.0;
-  s->runs = 0;
   for (auto& v : s->log_tick) v.clear();
   for (auto& v : s->log_site) v.clear();
   return SR_OK;
@@ -658,8 +673,11 @@ extern "C" int sr_save(sr_sim* s, void* blob, size_t cap, size_t* n) {
   std::memcpy(h.magic, "SRCKPT1", 8);
   h.p = s->p;
   h.p.init_spins = nullptr;
-  h.t_c = s->st.t_c; h.windows = s->windows; h.iterations = s->iterations; h.events = s->events;
-  h.last_g = s->last_g; h.last_f = s->last_f; h.nsub = s->L.nsub;
+  sr_obs o;
+  int rc = sr_observables(s, &o);
+  if (rc != SR_OK) return rc;
+  h.t_c = s->st.t_c; h.windows = s->windows; h.iterations = s->iterations; h.events = o.events_processed;
+  h.last_g = s->last_g; h.last_f = o.last_f; h.nsub = s->L.nsub;
   char* b = (char*)blob;
   std::memcpy(b, &h, sizeof(h));
   HIP_OR_FAIL(s, hipMemcpyAsync(b + sizeof(h), spins_at(s->L, s->st.wp), nsite, hipMemcpyDeviceToHost, s->stream));
@@ -684,8 +702,8 @@ extern "C" int sr_load(const void* blob, size_t n, void* stream, sr_sim** out) {
   HIP_OR_FAIL(s, hipMemcpyAsync(carry_at(s->L, 0), b + sizeof(h) + nsite, (size_t)h.nsub * sizeof(Carry), hipMemcpyHostToDevice, s->stream));
   HIP_OR_FAIL(s, hipStreamSynchronize(s->stream));
   s->st.t_c = h.t_c; s->st.wp = 0;
-  s->windows = h.windows; s->iterations = h.iterations; s->events = h.events;
-  s->last_g = h.last_g; s->last_f = h.last_f;
+  s->windows = h.windows; s->iterations = h.iterations; s->events_base = h.events;
+  s->last_g = h.last_g;
   return SR_OK;
 }
 
@@ -806,12 +824,10 @@ extern "C" int sr_batch_step(sr_sim* const* sims, int32_t n, int32_t max_windows
     s->W = r.W;
     s->windows += r.windows;
     s->iterations += r.iterations;
-    s->events += r.events;
-    if (r.windows) { s->last_g = r.last_g; s->last_f = r.last_f; }
+    if (r.windows) s->last_g = r.last_g;
     s->relax_launches += 1;
     s->relax_ms += ms;
     s->batch_tasks += r.tasks;
-    s->runs += r.runs;
     int one = SR_OK;
     if (r.status == kOverflow) {
       // grow, then run this step's windows alone from the last committed one

@@ -13,6 +13,7 @@ constexpr int64_t kTickInf = (int64_t)1 << 62;  // "no pending event"
 constexpr int kEdges = 4;                // boundary lists: N, S, W, E
 enum Edge { kN = 0, kS = 1, kW = 2, kE = 3 };
 constexpr int kPosBits = 16;             // history entry = tick << 16 | position
+constexpr int kMaxHistCap = 1024;        // entries per boundary list, at most
 
 // Per-subdomain state at committed time (or at a working window end).
 struct alignas(64) Carry {
@@ -22,34 +23,52 @@ struct alignas(64) Carry {
   uint64_t digest;   // order-free digest of committed events
   int64_t flips;     // committed flips
   int64_t wflips;    // flips of the working window (used by commit)
-  int64_t pad[2];
+  int64_t nbound;    // boundary-site events of the window (the paper's f
+                     // for this subdomain)
+  int64_t pad;
+};
+
+// Work counters of one subdomain (owned by the wave that runs it: read at the
+// start of a run, written at its end; summed by the host on request).
+struct SubStat {
+  unsigned long long events;  // events simulated, re-simulations included
+  unsigned long long runs;    // relaxation runs
 };
 
 // Snapshot of one subdomain's simulation state inside a window: the state
 // after every event and break point with tick < T.  A later iteration whose
 // inputs first differ at tick >= T resumes here instead of at the window
-// start (same inputs before T give the same state at T).
+// start (same inputs before T give the same state at T).  Written by one
+// wave with two full-line vector stores: the class words of its 64 lanes,
+// then 32 metadata words from lanes 0..31 (layout kCk* below).
 struct alignas(256) Ckpt {
   uint64_t cls[64];        // class nibbles, one word per lane
-  uint32_t ncnt[16];       // class counts N_k (k < 10)
-  int64_t T;
-  uint64_t j, acc;
-  int64_t anchor;
-  uint64_t halo[4];        // N, S, W, E halo spins
-  uint64_t dsum;           // digest sum of the window-log entries flushed so far
-  int32_t nev, nbound;     // window events so far, of which on the boundary
-  int32_t nout[4];         // own boundary-list lengths
-  int32_t head;            // position in the merged neighbour-flip stream
-  int32_t pad[3];
+  uint64_t meta[32];
+};
+enum CkptWord {
+  kCkCounts = 0,           // words 0..4: N_{2w} | N_{2w+1} << 32 (class counts)
+  kCkT = 5,                // T
+  kCkJ = 6,                // index of the pending random pair
+  kCkAcc = 7,              // integrated hazard
+  kCkAnchor = 8,
+  kCkHalo = 9,             // words 9..12: N, S, W, E halo spins
+  kCkDsum = 13,            // digest sum of the window-log entries flushed so far
+  kCkNev = 14,             // window events so far | (of which on the boundary) << 32
+  kCkOut01 = 15,           // own boundary-list lengths N | S << 32
+  kCkOut23 = 16,           // W | E << 32
+  kCkHead = 17,            // position in the merged neighbour-flip stream
+  kCkWords = 18
 };
 
-// Per-iteration flags, cleared before every iteration.
+// Per-iteration flags, cleared before every iteration.  Set with plain
+// stores of the value 1 (idempotent, so no read-modify-write on one shared
+// line by thousands of waves); visible to the next launch, or to the batched
+// decider through its release / acquire fences.
 struct IterFlags {
   uint32_t changed;      // some boundary history differs from the previous iteration
-  uint32_t overflow;     // some history / window-log buffer overflowed
-  uint32_t fmax;         // max boundary-site events of one subdomain
-  uint32_t runs;         // subdomains that ran (the others kept their outputs)
-  unsigned long long events;  // events simulated in this iteration
+  uint32_t ovf_hist;     // some boundary list overflowed
+  uint32_t ovf_log;      // some window log overflowed (or a run was cut short)
+  uint32_t pad;
 };
 
 // Everything one relaxation iteration of one lattice needs.
@@ -80,6 +99,7 @@ struct Lattice {
   unsigned long long* need;  // batched form: 2 x ceil(nsub/64) bitmaps, by
                           // iteration parity: subdomains to run in that
                           // iteration (set by the runs of the one before)
+  SubStat* stat;          // [nsub]
   uint64_t* wlog;         // [nsub][wcap]: tick << 16 | local site
   uint32_t* wcnt;         // [nsub]
   IterFlags* flags;       // [kMaxBatch], one per queued iteration
@@ -132,9 +152,8 @@ struct LatRun {
   int32_t remaining;       // tasks of the current iteration still running
   int32_t max_iters;
   int32_t status;          // kRunning, kDone, kOverflow, kNoConv
-  int32_t last_g, last_f;
-  uint32_t fmax_win;
-  int64_t windows, iterations, events, tasks, runs;
+  int32_t last_g;
+  int64_t windows, iterations, tasks;
   int32_t tune;            // adapt W after every window (see tune_window)
   int32_t win_budget;      // windows to commit in this launch (< 0: no limit)
   int64_t Wmin, Wmax;

@@ -203,10 +203,9 @@ __device__ __forceinline__ uint64_t merged_pop(Merged& s, int lane) {
   return e;
 }
 
-// First tick at which the own list just written (`cur`, n entries) differs
+// First tick at which the own list of this run (`cur`, n entries) differs
 // from the previous iteration's (`prev`, np entries); both agree on their
-// first n0 entries.  kTickInf if equal.  `cur` was written by this wave's
-// lanes: it is read with coherent loads after the caller's fence.
+// first n0 entries.  kTickInf if equal.  Both lists are in this wave's LDS.
 __device__ __forceinline__ int64_t first_change(const uint64_t* cur, int n, const uint64_t* prev, int np,
                                                 int n0, int lane) {
   const int m = n < np ? n : np;
@@ -215,7 +214,7 @@ __device__ __forceinline__ int64_t first_change(const uint64_t* cur, int n, cons
     bool diff = false;
     uint64_t x = 0, y = 0;
     if (i >= n0 && i < m) {
-      x = __hip_atomic_load(&cur[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      x = cur[i];
       y = prev[i];
       diff = x != y;
     }
@@ -229,9 +228,7 @@ __device__ __forceinline__ int64_t first_change(const uint64_t* cur, int n, cons
   }
   if (n == np) return kTickInf;
   // one list is a prefix of the other: the first extra entry
-  uint64_t e = 0;
-  if (lane == 0) e = n > np ? __hip_atomic_load(&cur[m], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : prev[m];
-  e = rdl64(e, 0);
+  const uint64_t e = n > np ? cur[m] : prev[m];
   return (int64_t)(e >> kPosBits);
 }
 
@@ -251,11 +248,13 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
   return x;
 }
 
-// LDS bytes one relaxation wave needs: the halo tile, or the raw and merged
-// neighbour lists (4 lists of up to hcap entries each), whichever is larger.
+// LDS bytes one relaxation wave needs: the halo tile, or the lists
+// (whichever is larger): the four raw neighbour lists (reused for the own
+// lists of the run once merged), the merged stream, and the four own lists of
+// the previous iteration, up to hcap entries each.
 __host__ __device__ inline size_t relax_lds_bytes(int bx, int by, int hcap) {
   size_t tile = (size_t)(bx + 2) * (by + 2);
-  size_t lists = (size_t)2 * 4 * hcap * sizeof(uint64_t);
+  size_t lists = (size_t)3 * 4 * hcap * sizeof(uint64_t);
   size_t b = tile > lists ? tile : lists;
   return (b + 15) & ~(size_t)15;
 }
@@ -308,7 +307,7 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
     edge_change(de, kW, wrapx);
     const int nck = (int)L.ckn[d];
     const Ckpt* cks = L.ck + (size_t)d * L.nck;
-    bool ok = lane < nck && cks[lane < nck ? lane : 0].T <= tau;
+    bool ok = lane < nck && (int64_t)cks[lane < nck ? lane : 0].meta[kCkT] <= tau;
     uint64_t m = ballot(ok);
     if (m) ck = 63 - __builtin_clzll(m);
   }
@@ -320,13 +319,18 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
   if (ck >= 0) {
     const Ckpt* c = L.ck + (size_t)d * L.nck + ck;
     cls = c->cls[lane];
-    ncnt = lane < 16 ? c->ncnt[lane & 15] : 0u;
-    hN = c->halo[0]; hS = c->halo[1]; hW = c->halo[2]; hE = c->halo[3];
-    j = c->j; acc = c->acc; anchor = c->anchor; dtot = c->dsum;
-    nev = c->nev; nbound = c->nbound;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) n0[e] = c->nout[e];
-    h0 = c->head;
+    const uint64_t mw = lane < kCkWords ? c->meta[lane] : 0ull;
+    const uint64_t pair = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(mw >> 32), lane >> 1, 64) << 32) |
+                          (uint32_t)__shfl((int)(uint32_t)mw, lane >> 1, 64);
+    ncnt = lane < kClasses ? (uint32_t)(pair >> (32 * (lane & 1))) : 0u;
+    hN = rdl64(mw, kCkHalo + 0); hS = rdl64(mw, kCkHalo + 1);
+    hW = rdl64(mw, kCkHalo + 2); hE = rdl64(mw, kCkHalo + 3);
+    j = rdl64(mw, kCkJ); acc = rdl64(mw, kCkAcc); anchor = (int64_t)rdl64(mw, kCkAnchor);
+    dtot = rdl64(mw, kCkDsum);
+    nev = (int)rdl(mw, kCkNev); nbound = (int)rdl((uint32_t)(mw >> 32), kCkNev);
+    n0[0] = (int)rdl(mw, kCkOut01); n0[1] = (int)rdl((uint32_t)(mw >> 32), kCkOut01);
+    n0[2] = (int)rdl(mw, kCkOut23); n0[3] = (int)rdl((uint32_t)(mw >> 32), kCkOut23);
+    h0 = (int)rdl(mw, kCkHead);
   } else {
     // committed block + one-site halo -> LDS (internal wrap falls out of the
     // periodic global index when the block spans the torus)
@@ -379,9 +383,14 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
 
   // ---- neighbour histories of the previous iteration (break points), each
   // in the slot its owner last wrote; the first iteration assumes none
-  // (canonical assumption).  Merge the four into one stream in LDS.
+  // (canonical assumption).  Merged into one stream in LDS.  The previous
+  // iteration's own lists come to LDS in the same pass: the end-of-run
+  // comparison then reads no global memory (a load there would wait for
+  // every store the run issued).
   uint64_t* raw = reinterpret_cast<uint64_t*>(lds);
   uint64_t* mrg = raw + 4 * hcap;
+  uint64_t* lprev = raw + 8 * hcap;
+  uint64_t* lcur = raw;                  // own lists of this run, once merged
   int ni[4];
   const uint64_t* li[4];
   {
@@ -395,17 +404,28 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
       ni[q] = none[q] ? 0 : clampn(hcnt_at(L, sl)[ev[q] * kEdges + ed[q]]);
     }
   }
-  const int o1 = ni[0], o2 = o1 + ni[1], o3 = o2 + ni[2], tot = o3 + ni[3];
-  if (tot > 0) {
+  const uint64_t* pb = hist_at(L, sprev) + (size_t)d * kEdges * hcap;
+  int np[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int oq = q == 0 ? 0 : q == 1 ? o1 : q == 2 ? o2 : o3;
-      for (int i = lane; i < ni[q]; i += 64) {
-        uint64_t x = li[q][i];
-        raw[oq + i] = ((x >> kPosBits) << kKeyShift) | ((uint64_t)q << 16) | (x & 0xFFFF);
-      }
+  for (int e = 0; e < 4; ++e) np[e] = first ? 0 : clampn(hcnt_at(L, sprev)[d * kEdges + e]);
+  const int o1 = ni[0], o2 = o1 + ni[1], o3 = o2 + ni[2], tot = o3 + ni[3];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int oq = q == 0 ? 0 : q == 1 ? o1 : q == 2 ? o2 : o3;
+    for (int i = lane; i < ni[q]; i += 64) {
+      uint64_t x = li[q][i];
+      raw[oq + i] = ((x >> kPosBits) << kKeyShift) | ((uint64_t)q << 16) | (x & 0xFFFF);
     }
-    __syncthreads();
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    for (int i = lane; i < np[e]; i += 64) lprev[e * hcap + i] = pb[e * hcap + i];
+  // committed digest and flip count of this subdomain, needed at the end
+  const uint64_t dig_in = rdl64(cin->digest, 0);
+  const int64_t flips_in = (int64_t)rdl64((uint64_t)cin->flips, 0);
+  const unsigned long long ev_in = rdl64(L.stat[d].events, 0), runs_in = rdl64(L.stat[d].runs, 0);
+  __syncthreads();
+  if (tot > 0) {
     for (int i = lane; i < tot; i += 64) {
       const int q = i < o1 ? 0 : i < o2 ? 1 : i < o3 ? 2 : 3;
       const int oq = q == 0 ? 0 : q == 1 ? o1 : q == 2 ? o2 : o3;
@@ -422,19 +442,16 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
   Merged in;
   merged_open(in, mrg, tot, h0, lane);
 
-  // ---- own lists of this iteration, written straight into the other slot
-  // (the previous version's first n0 entries copied over when resuming)
+  // ---- own lists of this iteration, built in LDS (when resuming, the
+  // previous version's first n0 entries, which the same inputs reproduce)
+  // and stored to the other slot at the end of the run
   uint64_t* ob = hist_at(L, sout) + (size_t)d * kEdges * hcap;
-  const uint64_t* pb = hist_at(L, sprev) + (size_t)d * kEdges * hcap;
-  int np[4];
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    np[e] = first ? 0 : clampn(hcnt_at(L, sprev)[d * kEdges + e]);
-    for (int i = lane; i < n0[e]; i += 64) ob[e * hcap + i] = pb[e * hcap + i];
-  }
+  for (int e = 0; e < 4; ++e)
+    for (int i = lane; i < n0[e]; i += 64) lcur[e * hcap + i] = lprev[e * hcap + i];
   int nN = n0[0], nS = n0[1], nW = n0[2], nE = n0[3];
   auto push = [&](int e, int& n, uint64_t x) {
-    if (lane == 0 && n < hcap) ob[e * hcap + n] = x;
+    if (lane == 0 && n < hcap) lcur[e * hcap + n] = x;
     n++;
   };
 
@@ -495,15 +512,24 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
       // state after every item with tick < tn: a place to resume from
       Ckpt* c = ckbase + ckc;
       c->cls[lane] = cls;
-      if (lane < 16) c->ncnt[lane] = ncnt;
-      if (lane == 0) {
-        c->T = tn; c->j = j; c->acc = acc; c->anchor = anchor;
-        c->halo[0] = hN; c->halo[1] = hS; c->halo[2] = hW; c->halo[3] = hE;
-        c->dsum = dtot;                  // log entries flushed so far
-        c->nev = nev; c->nbound = nbound;
-        c->nout[0] = nN; c->nout[1] = nS; c->nout[2] = nW; c->nout[3] = nE;
-        c->head = in.head;
-      }
+      // metadata word `lane` (dsum: the log entries flushed so far)
+      const uint32_t clo = (uint32_t)__shfl((int)ncnt, (2 * lane) & 63, 64);
+      const uint32_t chi = (uint32_t)__shfl((int)ncnt, (2 * lane + 1) & 63, 64);
+      uint64_t w = (uint64_t)clo | ((uint64_t)chi << 32);
+      w = lane == kCkT ? (uint64_t)tn : w;
+      w = lane == kCkJ ? j : w;
+      w = lane == kCkAcc ? acc : w;
+      w = lane == kCkAnchor ? (uint64_t)anchor : w;
+      w = lane == kCkHalo + 0 ? hN : w;
+      w = lane == kCkHalo + 1 ? hS : w;
+      w = lane == kCkHalo + 2 ? hW : w;
+      w = lane == kCkHalo + 3 ? hE : w;
+      w = lane == kCkDsum ? dtot : w;
+      w = lane == kCkNev ? ((uint64_t)(uint32_t)nev | ((uint64_t)(uint32_t)nbound << 32)) : w;
+      w = lane == kCkOut01 ? ((uint64_t)(uint32_t)nN | ((uint64_t)(uint32_t)nS << 32)) : w;
+      w = lane == kCkOut23 ? ((uint64_t)(uint32_t)nW | ((uint64_t)(uint32_t)nE << 32)) : w;
+      w = lane == kCkHead ? (uint64_t)(uint32_t)in.head : w;
+      if (lane < 32) c->meta[lane] = lane < kCkWords ? w : 0ull;
       ckc++;
       since = 0;
     }
@@ -599,28 +625,40 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
   if (nev & 63) log_flush(nev & 63);
 
   // end-of-window block -> working lattice (the other window parity)
+  // (a lane's S sites are consecutive in one row and S-byte aligned, since
+  // bx, x0 and Lx are multiples of S: one store per lane)
   int8_t* so = spins_at(L, st.wp ^ 1);
   {
-    const int base = lane << sh;
-    for (int i = 0; i < S; ++i) {
-      int v = base + i;
-      if (v < nblk) {
-        int ly = v / bx, lx = v - ly * bx;
-        int k = (int)((cls >> (4 * i)) & 15);
-        so[(int64_t)(y0 + ly) * L.Lx + x0 + lx] = (int8_t)(k < 5 ? 1 : -1);
+    const int v = lane << sh;
+    if (v < nblk) {
+      const int ly = v / bx, lx = v - ly * bx;
+      int8_t* dst = so + (int64_t)(y0 + ly) * L.Lx + x0 + lx;
+      uint64_t b[2] = {0ull, 0ull};
+      for (int i = 0; i < S; ++i) {
+        const uint64_t sb = ((cls >> (4 * i)) & 15) < 5 ? 0x01ull : 0xFFull;
+        b[i >> 3] |= sb << (8 * (i & 7));
+      }
+      if (S == 1) *dst = (int8_t)b[0];
+      else if (S == 2) *reinterpret_cast<uint16_t*>(dst) = (uint16_t)b[0];
+      else if (S == 4) *reinterpret_cast<uint32_t*>(dst) = (uint32_t)b[0];
+      else {
+        reinterpret_cast<uint64_t*>(dst)[0] = b[0];
+        if (S == 16) reinterpret_cast<uint64_t*>(dst)[1] = b[1];
       }
     }
   }
-  // compare step (c): own lists against the previous iteration's
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  // compare step (c): own lists against the previous iteration's, then the
+  // own lists to their slot (coalesced)
   const int nn[4] = {nN, nS, nW, nE};
   int64_t fc[4];
 #pragma unroll
-  for (int e = 0; e < 4; ++e)
-    fc[e] = first ? (nn[e] > 0 ? (int64_t)(__hip_atomic_load(&ob[e * hcap], __ATOMIC_RELAXED,
-                                                             __HIP_MEMORY_SCOPE_AGENT) >> kPosBits)
-                               : kTickInf)
-                  : first_change(ob + e * hcap, clampn((uint32_t)nn[e]), pb + e * hcap, np[e], n0[e], lane);
+  for (int e = 0; e < 4; ++e) {
+    const int n = clampn((uint32_t)nn[e]);
+    const uint64_t* cur = lcur + e * hcap;
+    fc[e] = first ? (n > 0 ? (int64_t)(cur[0] >> kPosBits) : kTickInf)
+                  : first_change(cur, n, lprev + e * hcap, np[e], n0[e], lane);
+    for (int i = lane; i < n; i += 64) ob[e * hcap + i] = cur[i];
+  }
   uint32_t* cnt_out = hcnt_at(L, sout) + d * kEdges;
   int64_t* fct_out = fct_at(L, sout) + d * kEdges;
   if (lane == 0) {
@@ -633,16 +671,19 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
     }
     Carry* co = &carry_at(L, st.wp ^ 1)[d];
     co->j = j; co->anchor = anchor; co->acc = acc;
-    co->digest = cin->digest + dtot;
-    co->flips = cin->flips + nev;
+    co->digest = dig_in + dtot;
+    co->flips = flips_in + nev;
     co->wflips = nev;
+    co->nbound = nbound;
+    L.stat[d].events = ev_in + (unsigned long long)(nev - nev0);
+    L.stat[d].runs = runs_in + 1ull;
     L.wcnt[d] = (uint32_t)nev;
     L.ckn[d] = (uint32_t)ckc;
     slot_at(L, st.it & 1)[d] = (uint8_t)sout;
     chg_at(L, st.it & 1)[d] = (uint8_t)emask;
     uint32_t ovf = ((nN > hcap || nS > hcap || nW > hcap || nE > hcap) ? 1u : 0u) |
                    ((nev > wcap || runaway) ? 2u : 0u);
-    if (emask) atomicOr(&fl->changed, 1u);
+    if (emask) fl->changed = 1u;
     if (L.need && emask) {
       // batched form: the neighbour facing each changed edge runs next time
       unsigned long long* nb = need_at(L, (st.it + 1) & 1);
@@ -651,10 +692,8 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
       for (int e = 0; e < 4; ++e)
         if (emask & (1u << e)) atomicOr(&nb[facing[e] >> 6], 1ull << (facing[e] & 63));
     }
-    if (ovf) atomicOr(&fl->overflow, ovf);
-    atomicMax(&fl->fmax, (uint32_t)nbound);
-    atomicAdd(&fl->runs, 1u);
-    atomicAdd(&fl->events, (unsigned long long)(nev - nev0));
+    if (ovf & 1u) fl->ovf_hist = 1u;
+    if (ovf & 2u) fl->ovf_log = 1u;
   }
 }
 
@@ -683,7 +722,7 @@ __global__ __launch_bounds__(64) void relax_kernel(Lattice L, Step st) {
     // queued behind an iteration that already converged (or overflowed):
     // nothing to do
     const IterFlags* fp = L.flags + st.fi - 1;
-    if (fp->changed == 0 || fp->overflow != 0) return;
+    if (fp->changed == 0 || fp->ovf_hist != 0 || fp->ovf_log != 0) return;
   }
   if (st.it > 0 && !inputs_changed(L, st.it, d)) {
     // keep the previous outputs (lists, window state, log): skip the run
@@ -709,7 +748,7 @@ __global__ __launch_bounds__(64) void relax_graph_kernel(Lattice L, const Step* 
   st.t_c = cs.t_c; st.t_end = cs.t_end; st.wp = cs.wp; st.it = cs.it + i; st.fi = i; st.pad = 0;
   if (i > 0) {
     const IterFlags* fp = L.flags + i - 1;
-    if (fp->changed == 0 || fp->overflow != 0) return;
+    if (fp->changed == 0 || fp->ovf_hist != 0 || fp->ovf_log != 0) return;
   }
   if (st.it > 0 && !inputs_changed(L, st.it, d)) {
     if (lane_id() == 0) {
@@ -726,7 +765,7 @@ __global__ __launch_bounds__(64) void relax_graph_kernel(Lattice L, const Step* 
 __global__ void clear_flags_kernel(IterFlags* f, int n) {
   int i = threadIdx.x;
   if (i < n) {
-    f[i].changed = 0; f[i].overflow = 0; f[i].fmax = 0; f[i].runs = 0; f[i].events = 0;
+    f[i].changed = 0; f[i].ovf_hist = 0; f[i].ovf_log = 0; f[i].pad = 0;
   }
 }
 
@@ -754,9 +793,8 @@ __device__ __forceinline__ Step load_step(const Step* p) {
 }
 __device__ __forceinline__ IterFlags load_flags(const IterFlags* p) {
   IterFlags f;
-  f.changed = u32s(p->changed); f.overflow = u32s(p->overflow); f.fmax = u32s(p->fmax);
-  f.runs = u32s(p->runs);
-  f.events = (unsigned long long)u64s(reinterpret_cast<const int64_t&>(p->events));
+  f.changed = u32s(p->changed); f.ovf_hist = u32s(p->ovf_hist); f.ovf_log = u32s(p->ovf_log);
+  f.pad = 0;
   return f;
 }
 
@@ -833,14 +871,9 @@ __device__ void decide(const BatchArgs& B, int lat, int lane) {
   const IterFlags f = load_flags(&run->fl);
   Step st = load_step(&run->st);
   bool finish = false;
-  if (lane == 0) {
-    run->iterations += 1;
-    run->events += (int64_t)f.events;
-    run->runs += (int64_t)f.runs;
-    run->fmax_win = max(run->fmax_win, f.fmax);
-  }
+  if (lane == 0) run->iterations += 1;
   int next_it = -1;
-  if (f.overflow) {
+  if (f.ovf_hist || f.ovf_log) {
     if (lane == 0) run->status = kOverflow;
     finish = true;
   } else if (f.changed) {
@@ -858,8 +891,6 @@ __device__ void decide(const BatchArgs& B, int lat, int lane) {
     if (lane == 0) {
       run->windows = wins;
       run->last_g = st.it + 1;
-      run->last_f = (int32_t)run->fmax_win;
-      run->fmax_win = 0;
     }
     int64_t W = u64s(run->W);
     if (run->tune) {
@@ -887,7 +918,7 @@ __device__ void decide(const BatchArgs& B, int lat, int lane) {
   st.fi = 0;
   if (lane == 0) {
     run->st = st;
-    run->fl.changed = 0; run->fl.overflow = 0; run->fl.fmax = 0; run->fl.runs = 0; run->fl.events = 0;
+    run->fl.changed = 0; run->fl.ovf_hist = 0; run->fl.ovf_log = 0;
   }
   if (enqueue_iteration(B, lat, run, L, next_it, lane) == 0) {
     // a changed iteration must schedule some subdomain; never wait forever

@@ -50,6 +50,7 @@ static void tuned() {
   }
   CHECK(sr_observables(s, &o) == SR_OK);
   CHECK(o.tick == o.horizon_ticks && o.windows == total);
+  CHECK(o.subdomain_runs == o.iterations * o.n_sub);   // every subdomain, every iteration
   CHECK(total > predicted);
   CHECK(sr_run_window(s, -1, nullptr, &done) == SR_OK && done == 0);
   sr_destroy(s);

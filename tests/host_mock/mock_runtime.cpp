@@ -68,20 +68,28 @@ hipError_t hipGetLastError() { return hipSuccess; }
 hipError_t hipGetDevice(int* d) { *d = 0; return hipSuccess; }
 hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t, int) { *v = 256; return hipSuccess; }
 
-// A "graph" of k relaxation iterations: remembers where the flags and the
-// window descriptor live, as the captured kernels do.
+// A "graph" of k relaxation iterations: remembers the lattice descriptor and
+// where the window descriptor lives, as the captured kernels do.
 struct ihipGraphExec_t {
-  sr::IterFlags* flags;
+  sr::Lattice L;
   const sr::Step* dstep;
-  int k, nsub;
+  int k;
 };
-static void relax_flags(sr::IterFlags* f, int it, int nsub) {
+static void relax_flags(sr::IterFlags* f, int it) {
   std::memset(f, 0, sizeof(*f));
   f->changed = it < env_int("SR_MOCK_G", 1) - 1;
-  f->runs = (uint32_t)nsub;
 }
+static void count_runs(const sr::Lattice& L) {
+  for (int d = 0; d < L.nsub; ++d) L.stat[d].runs += 1;
+}
+// Iterations queued behind one that converged do nothing, as on the device.
+static bool queued_after_convergence(const sr::IterFlags* f, int fi) { return fi > 0 && !f[fi - 1].changed; }
 hipError_t hipGraphLaunch(hipGraphExec_t g, hipStream_t) {
-  for (int i = 0; i < g->k; ++i) relax_flags(&g->flags[i], g->dstep->it + i, g->nsub);
+  for (int i = 0; i < g->k; ++i) {
+    if (queued_after_convergence(g->L.flags, i)) continue;
+    relax_flags(&g->L.flags[i], g->dstep->it + i);
+    count_runs(g->L);
+  }
   return hipSuccess;
 }
 hipError_t hipGraphExecDestroy(hipGraphExec_t g) {
@@ -93,7 +101,9 @@ extern "C" size_t sr_mock_live_allocations() { return g_dev.size() + g_host.size
 
 namespace sr {
 hipError_t launch_relax(const Lattice& L, const Step& st, hipStream_t) {
-  relax_flags(&L.flags[st.fi], st.it, L.nsub);
+  if (queued_after_convergence(L.flags, st.fi)) return hipSuccess;
+  relax_flags(&L.flags[st.fi], st.it);
+  count_runs(L);
   return hipSuccess;
 }
 hipError_t launch_init_random(int8_t* s, int64_t n, uint64_t seed, hipStream_t) {
@@ -136,7 +146,7 @@ hipError_t launch_batch(const BatchArgs& B, int, size_t, hipStream_t) {
 int batch_waves_per_cu(size_t) { return 4; }
 size_t relax_lds(const Lattice& L) { return 1024 + 64 * (size_t)L.hcap; }
 hipError_t build_window_graph(const Lattice& L, const Step* dstep, int k, hipGraphExec_t* out) {
-  *out = new ihipGraphExec_t{L.flags, dstep, k, L.nsub};
+  *out = new ihipGraphExec_t{L, dstep, k};
   return hipSuccess;
 }
 }  // namespace sr
