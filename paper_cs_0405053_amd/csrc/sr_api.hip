@@ -745,14 +745,19 @@ extern "C" int sr_batch_step(sr_sim* const* sims, int32_t n, int32_t max_windows
   HIP_OR_FAIL(s0, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   int per_cu = batch_waves_per_cu(lds);
   if (per_cu <= 0) SR_FAIL(s0, SR_EDEVICE, "cannot size the persistent grid");
-  int waves = per_cu * ncu;
+  int waves = std::max(per_cu * ncu, kShards);   // every shard needs a wave
+  // a shard's ring holds its share of every lattice's current iteration
+  // (tasks are dealt round-robin, at most one extra per lattice) plus the
+  // tickets its waves may hold ahead of production
   uint64_t qn = 1;
-  while (qn < total + (uint64_t)waves + 64) qn <<= 1;
+  while (qn < total / kShards + (uint64_t)idx.size() + (uint64_t)waves / kShards + 64) qn <<= 1;
 
   std::vector<Lattice> lat(m);
   std::vector<LatRun> run(m);
-  std::vector<unsigned long long> q(qn, 0ull);
-  uint64_t t = 0;
+  std::vector<unsigned long long> q(kShards * qn, 0ull);
+  std::vector<ShardRem> rem((size_t)m * kShards);
+  std::memset(rem.data(), 0, rem.size() * sizeof(ShardRem));
+  uint64_t fill[kShards] = {};
   for (int k = 0; k < m; ++k) {
     sr_sim* s = sims[idx[k]];
     lat[k] = s->L;
@@ -764,45 +769,54 @@ extern "C" int sr_batch_step(sr_sim* const* sims, int32_t n, int32_t max_windows
     r.st.it = 0; r.st.fi = 0;
     r.st.t_end = std::min(s->st.t_c + s->W, s->H);
     r.H = s->H; r.W = s->W;
-    r.remaining = s->L.nsub;
+    r.shards_left = std::min(s->L.nsub, kShards);
     r.max_iters = s->p.max_iters;
     r.status = kRunning;
     r.tasks = s->L.nsub;
     r.tune = s->tune ? 1 : 0;
     r.win_budget = max_windows > 0 ? max_windows : -1;
     r.Wmin = s->Wmin; r.Wmax = s->Wmax;
-    for (int d = 0; d < s->L.nsub; ++d, ++t)
-      q[t] = ((unsigned long long)(t + 1) << 32) | ((unsigned long long)k << 20) | (unsigned)d;
+    // the first iteration runs every subdomain: task d goes to shard
+    // (k + d) % kShards, as the device decider deals later iterations
+    for (int d = 0; d < s->L.nsub; ++d) {
+      const int g = (k % kShards + d) % kShards;
+      const uint64_t at = fill[g]++;
+      q[(size_t)g * qn + at] = ((unsigned long long)(at + 1) << 32) | ((unsigned long long)k << 20) | (unsigned)d;
+      rem[(size_t)k * kShards + g].n++;
+    }
   }
   Lattice* dlat = nullptr;
   LatRun* drun = nullptr;
   unsigned long long* dq = nullptr;
   BatchCounters* dctr = nullptr;
+  ShardRem* drem = nullptr;
   auto release = [&]() {
     if (dlat) (void)hipFree(dlat);
     if (drun) (void)hipFree(drun);
     if (dq) (void)hipFree(dq);
     if (dctr) (void)hipFree(dctr);
+    if (drem) (void)hipFree(drem);
   };
   if (hipMalloc(&dlat, m * sizeof(Lattice)) != hipSuccess || hipMalloc(&drun, m * sizeof(LatRun)) != hipSuccess ||
-      hipMalloc(&dq, qn * sizeof(unsigned long long)) != hipSuccess || hipMalloc(&dctr, sizeof(BatchCounters)) != hipSuccess) {
+      hipMalloc(&dq, q.size() * sizeof(unsigned long long)) != hipSuccess ||
+      hipMalloc(&dctr, sizeof(BatchCounters)) != hipSuccess ||
+      hipMalloc(&drem, rem.size() * sizeof(ShardRem)) != hipSuccess) {
     release();
     SR_FAIL(s0, SR_ENOMEM, "cannot allocate the batch queue");
   }
   BatchCounters ctr;
   std::memset(&ctr, 0, sizeof(ctr));
-  ctr.head = 0; ctr.tail = total; ctr.done = 0;
+  for (int g = 0; g < kShards; ++g) { ctr.sh[g].head = 0; ctr.sh[g].tail = fill[g]; }
+  ctr.done = 0;
   BatchArgs args;
-  args.ctr = dctr; args.q = dq; args.lat = dlat; args.run = drun;
+  args.ctr = dctr; args.q = dq; args.lat = dlat; args.run = drun; args.rem = drem;
   args.nlat = (uint32_t)m; args.qmask = (uint32_t)(qn - 1);
-  args.take = 1;
-  if (const char* tk = std::getenv("SR_BATCH_TAKE")) args.take = std::max(1, std::min(4, std::atoi(tk)));
-  args.pad = 0;
   hipEvent_t e0 = s0->ev[0], e1 = s0->ev[1];
   int rc = SR_OK;
   if (hipMemcpyAsync(dlat, lat.data(), m * sizeof(Lattice), hipMemcpyHostToDevice, stream) != hipSuccess ||
       hipMemcpyAsync(drun, run.data(), m * sizeof(LatRun), hipMemcpyHostToDevice, stream) != hipSuccess ||
-      hipMemcpyAsync(dq, q.data(), qn * sizeof(unsigned long long), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(dq, q.data(), q.size() * sizeof(unsigned long long), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(drem, rem.data(), rem.size() * sizeof(ShardRem), hipMemcpyHostToDevice, stream) != hipSuccess ||
       hipMemcpyAsync(dctr, &ctr, sizeof(ctr), hipMemcpyHostToDevice, stream) != hipSuccess ||
       hipEventRecord(e0, stream) != hipSuccess || launch_batch(args, waves, lds, stream) != hipSuccess ||
       hipEventRecord(e1, stream) != hipSuccess ||

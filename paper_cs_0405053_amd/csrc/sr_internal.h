@@ -149,7 +149,7 @@ struct LatRun {
   Step st;                 // current window and iteration
   IterFlags fl;            // flags of the current iteration
   int64_t H, W;            // horizon and window (ticks)
-  int32_t remaining;       // tasks of the current iteration still running
+  int32_t shards_left;     // shards still running tasks of the current iteration
   int32_t max_iters;
   int32_t status;          // kRunning, kDone, kOverflow, kNoConv
   int32_t last_g;
@@ -175,23 +175,36 @@ __host__ __device__ inline int64_t tune_window(int64_t W, int g, int64_t Wmin, i
   return nw < 1 ? 1 : nw;
 }
 
-// Device work queue of (lattice, subdomain) tasks.  A slot holds
-// (ticket + 1) << 32 | lattice << 20 | subdomain; a consumer owning ticket p
-// waits until slot p & qmask carries p + 1.
-struct BatchCounters {
+// Device work queue of (lattice, subdomain) tasks, dealt over kShards shards.
+// Every atomic on these counters is performed at the memory side, so a single
+// shared ticket counter would serialise the whole grid: each shard is a ring
+// with its own head / tail on its own cache line, and a wave serves one
+// shard.  A slot holds (ticket + 1) << 32 | lattice << 20 | subdomain; a
+// consumer owning ticket p of a shard waits until slot p & qmask of that
+// shard's ring carries p + 1.
+constexpr int kShards = 8;
+struct alignas(128) ShardCtr {
   unsigned long long head;     // next ticket to hand to a consumer
   unsigned long long tail;     // next ticket to hand to a producer
-  uint32_t done;               // lattices finished
+};
+struct BatchCounters {
+  ShardCtr sh[kShards];
+  alignas(128) uint32_t done;  // lattices finished
   uint32_t abort;              // set when a wave waited far too long
+};
+// Tasks of one lattice's current iteration still running in one shard (own
+// cache line).  The last task of a shard then counts down the lattice's
+// shards_left; the last shard's last task decides the iteration.
+struct alignas(128) ShardRem {
+  int32_t n;
 };
 struct BatchArgs {             // read-only for the kernel's lifetime
   BatchCounters* ctr;
-  unsigned long long* q;
+  unsigned long long* q;       // kShards rings of qmask + 1 slots
   const Lattice* lat;
   LatRun* run;
+  ShardRem* rem;               // [nlat][kShards]
   uint32_t nlat, qmask;
-  int32_t take;                // tickets a wave may take at once (1..4)
-  int32_t pad;
 };
 
 }  // namespace sr

@@ -802,7 +802,8 @@ __device__ __forceinline__ IterFlags load_flags(const IterFlags* p) {
 // iteration `it`: all of them when it == 0, else those whose facing input
 // lists changed in iteration it - 1 (their bits in the need bitmap).  The
 // others keep their lists: the slot array is copied forward and the change
-// masks cleared before anything is published.  Sets run.remaining first.
+// masks cleared before anything is published.  Sets the per-shard counts
+// and shards_left before publishing any task.
 __device__ uint32_t enqueue_iteration(const BatchArgs& B, int lat, LatRun* run, CLattice& L, int it,
                                       int lane) {
   const int nsub = L.nsub;
@@ -825,15 +826,25 @@ __device__ uint32_t enqueue_iteration(const BatchArgs& B, int lat, LatRun* run, 
   }
   count = (uint32_t)wave_sum64(count);
   if (count == 0) return 0;                     // caller turns this into an error
+  // task i of the iteration goes to shard (off + i) % kShards, the
+  // (i / kShards)-th of that shard; lane s < kShards handles shard s
+  const int off = lat % kShards;
+  const int ls = (lane - off + kShards) % kShards;         // first task index of shard `lane`
+  const uint32_t ns = lane < kShards ? (count > (uint32_t)ls ? (count - 1 - ls) / kShards + 1 : 0u) : 0u;
+  if (lane < kShards) B.rem[(size_t)lat * kShards + lane].n = (int32_t)ns;
   if (lane == 0) {
-    run->remaining = (int32_t)count;
+    run->shards_left = (int32_t)(count < (uint32_t)kShards ? count : (uint32_t)kShards);
     run->tasks += count;
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  unsigned long long base = 0;
-  if (lane == 0) base = atomicAdd(&B.ctr->tail, (unsigned long long)count);
-  base = ((uint64_t)rdl((uint32_t)(base >> 32), 0) << 32) | rdl((uint32_t)base, 0);
+  unsigned long long sbase = 0;
+  if (lane < kShards && ns) sbase = atomicAdd(&B.ctr->sh[lane].tail, (unsigned long long)ns);
+  unsigned long long bases[kShards];           // wave-uniform, read before the divergent walk
+#pragma unroll
+  for (int k = 0; k < kShards; ++k) bases[k] = rdl64(sbase, k);
+  const size_t qn = (size_t)B.qmask + 1;
   // lane-major walk: word w of the bitmap, its set bits in ascending order
+  uint32_t done_before = 0;
   for (int w0 = 0; w0 < nw; w0 += 64) {
     unsigned long long m = 0;
     if (w0 + lane < nw) {
@@ -844,19 +855,23 @@ __device__ uint32_t enqueue_iteration(const BatchArgs& B, int lat, LatRun* run, 
       // dirty in this XCD's L2 and be written back over their bits)
       if (it > 0) __hip_atomic_store(&nb[w0 + lane], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    uint32_t c = (uint32_t)__popcll(m);
-    uint32_t excl = wave_incl_scan(c) - c;
-    uint32_t chunk_tot = rdl(wave_incl_scan(c), 63);
-    unsigned long long at = base + excl;
+    const uint32_t c = (uint32_t)__popcll(m);
+    const uint32_t incl = wave_incl_scan(c);
+    uint32_t i = done_before + incl - c;       // task index of this lane's first bit
     while (m) {
-      int bit = ctz64(m);
+      const int bit = ctz64(m);
       m &= m - 1;
-      int d = (w0 + lane) * 64 + bit;
-      unsigned long long v = ((at + 1) << 32) | ((unsigned long long)lat << 20) | (unsigned)d;
-      __hip_atomic_store(&B.q[at & B.qmask], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      at++;
+      const int d = (w0 + lane) * 64 + bit;
+      const int sh = (int)((off + i) % kShards);
+      unsigned long long base = bases[0];
+#pragma unroll
+      for (int k = 1; k < kShards; ++k) base = sh == k ? bases[k] : base;
+      const unsigned long long at = base + i / kShards;
+      const unsigned long long v = ((at + 1) << 32) | ((unsigned long long)lat << 20) | (unsigned)d;
+      __hip_atomic_store(&B.q[(size_t)sh * qn + (at & B.qmask)], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      i++;
     }
-    base += chunk_tot;
+    done_before += rdl(incl, 63);
   }
   return count;
 }
@@ -928,76 +943,55 @@ __device__ void decide(const BatchArgs& B, int lat, int lane) {
   }
 }
 
-// Tickets are taken one at a time, or up to kTake at once when that many are
-// already reserved by producers (then none of them can depend on a task this
-// wave holds, and one acquire and one release cover them all: the
-// agent-scope fences write back and invalidate the XCD caches, the costliest
-// step of a short task).
-constexpr int kTake = 4;
 // Empty polls of one queue slot before the kernel gives up (about ten
 // seconds; a task takes microseconds to milliseconds).
 constexpr uint32_t kSpinBudget = 20u << 20;
 
+// Wave w serves shard w % kShards (consecutive workgroups go to different
+// XCDs, so each shard's counters are hit mostly from one XCD).  Per task: one
+// ticket, wait for its slot, acquire, relax, release, count down.
 __global__ __launch_bounds__(64) void batch_kernel(BatchArgs B) {
   extern __shared__ int8_t tile[];
   const int lane = lane_id();
   CLattice* lats = (CLattice*)B.lat;
+  const int g = (int)(blockIdx.x % kShards);
+  ShardCtr* sc = &B.ctr->sh[g];
+  const unsigned long long* qg = B.q + (size_t)g * ((size_t)B.qmask + 1);
   for (;;) {
-    unsigned long long t0 = 0;
-    int k = 1;
-    if (lane == 0) {
-      unsigned long long h = __hip_atomic_load(&B.ctr->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      unsigned long long tl = __hip_atomic_load(&B.ctr->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      bool got = false;
-      if (B.take > 1 && tl > h + 1) {
-        int kk = (tl - h) >= (unsigned long long)B.take ? B.take : (int)(tl - h);
-        unsigned long long seen = atomicCAS(&B.ctr->head, h, h + (unsigned long long)kk);
-        if (seen == h) { t0 = h; k = kk; got = true; }
+    unsigned long long t = 0;
+    if (lane == 0) t = atomicAdd(&sc->head, 1ull);
+    t = ((uint64_t)rdl((uint32_t)(t >> 32), 0) << 32) | rdl((uint32_t)t, 0);
+    const uint32_t want = (uint32_t)(t + 1);
+    unsigned long long v;
+    uint32_t spins = 0;
+    for (;;) {
+      v = __hip_atomic_load(&qg[t & B.qmask], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if ((uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32)) == want) break;
+      if (__hip_atomic_load(&B.ctr->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= B.nlat) return;
+      if (__hip_atomic_load(&B.ctr->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+      if (++spins > kSpinBudget) {
+        // far longer than any task takes: give up rather than hang
+        if (lane == 0) __hip_atomic_store(&B.ctr->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
       }
-      if (!got) { t0 = atomicAdd(&B.ctr->head, 1ull); k = 1; }
+      __builtin_amdgcn_s_sleep(2);
     }
-    t0 = ((uint64_t)rdl((uint32_t)(t0 >> 32), 0) << 32) | rdl((uint32_t)t0, 0);
-    k = (int)rdl((uint32_t)k, 0);
-    // wait for the k slots; lane i keeps task i
-    uint32_t mine = 0;
-    for (int i = 0; i < k; ++i) {
-      const unsigned long long t = t0 + (unsigned long long)i;
-      const uint32_t want = (uint32_t)(t + 1);
-      unsigned long long v;
-      uint32_t spins = 0;
-      for (;;) {
-        v = __hip_atomic_load(&B.q[t & B.qmask], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if ((uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32)) == want) break;
-        if (__hip_atomic_load(&B.ctr->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= B.nlat) return;
-        if (__hip_atomic_load(&B.ctr->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-        if (++spins > kSpinBudget) {
-          // far longer than any task takes: give up rather than hang
-          if (lane == 0) __hip_atomic_store(&B.ctr->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          return;
-        }
-        __builtin_amdgcn_s_sleep(2);
-      }
-      if (lane == i) mine = (uint32_t)v;
-    }
+    // the task is wave-uniform: keep it (and all that derives from it) scalar
+    const uint32_t pay = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const int lat = (int)((pay >> 20) & 0xFFF);
+    const int d = (int)(pay & 0xFFFFF);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    for (int i = 0; i < k; ++i) {
-      // the task is wave-uniform: keep it (and all that derives from it) scalar
-      const uint32_t pay = rdl(mine, i);
-      const int lat = (int)((pay >> 20) & 0xFFF);
-      const int d = (int)(pay & 0xFFFFF);
-      LatRun* run = &B.run[lat];
-      const Step st = load_step(&run->st);
-      relax_subdomain(lats[lat], st, d, tile, &run->fl);
-    }
+    LatRun* run = &B.run[lat];
+    const Step st = load_step(&run->st);
+    relax_subdomain(lats[lat], st, d, tile, &run->fl);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    for (int i = 0; i < k; ++i) {
-      const uint32_t pay = rdl(mine, i);
-      const int lat = (int)((pay >> 20) & 0xFFF);
-      int last = 0;
-      if (lane == 0) last = (atomicSub(&B.run[lat].remaining, 1) == 1);
-      last = (int)rdl((uint32_t)last, 0);
-      if (last) decide(B, lat, lane);
+    int last = 0;
+    if (lane == 0) {
+      if (atomicSub(&B.rem[(size_t)lat * kShards + g].n, 1) == 1)
+        last = (atomicSub(&run->shards_left, 1) == 1);
     }
+    last = (int)rdl((uint32_t)last, 0);
+    if (last) decide(B, lat, lane);
   }
 }
 
