@@ -57,7 +57,7 @@ struct sr_sim {
   double relax_ms = 0.0;
   int64_t batch_tasks = 0;
   int failed = SR_OK;                   // last batched run ended in this error
-  unsigned long long* need = nullptr;   // batched form's need bitmaps
+  uint8_t* need = nullptr;              // batched form's "runs now" bytes
   double last_batch_ms = 0.0;
   // captured windows: graph of k iterations, keyed by k (rebuilt when the
   // buffers move); the window descriptor is read from dstep
@@ -236,7 +236,7 @@ static Plan plan(const sr_params& p, int64_t Wmax) {
   pl.bytes = 2 * nsite + 2 * nsub * sizeof(Carry) + 2 * nsub * kEdges * (sizeof(uint32_t) + sizeof(int64_t)) +
              4 * nsub + nsub * pl.nck * sizeof(Ckpt) + 2 * nsub * sizeof(uint32_t) +
              2 * nsub * kEdges * (size_t)pl.hcap * sizeof(uint64_t) + nsub * (size_t)pl.wcap * sizeof(uint64_t) +
-             2 * ((nsub + 63) / 64) * 8 + nsub * sizeof(SubStat) + (p.init == SR_INIT_USER ? nsite : 0) +
+             2 * (size_t)need_stride((int)nsub) + nsub * sizeof(SubStat) + (p.init == SR_INIT_USER ? nsite : 0) +
              64 * 1024;
   return pl;
 }
@@ -340,8 +340,8 @@ static int create_impl(const sr_params* pin, void* stream, sr_sim** out, bool in
   for (auto& e : s->ev)
     if (hipEventCreate(&e) != hipSuccess) return fail(SR_EDEVICE, "cannot create events");
   if (hipMalloc(&s->dstep, sizeof(Step)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate step");
-  if (hipMalloc(&s->need, 2 * (size_t)((L.nsub + 63) / 64) * sizeof(unsigned long long)) != hipSuccess)
-    return fail(SR_ENOMEM, "cannot allocate need bitmaps");
+  if (hipMalloc(&s->need, 2 * (size_t)need_stride(L.nsub)) != hipSuccess)
+    return fail(SR_ENOMEM, "cannot allocate run marks");
   if (hipHostMalloc(&s->hstep, sizeof(Step), hipHostMallocDefault) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate pinned step");
   {
     const char* ng = std::getenv("SR_NO_GRAPHS");
@@ -762,7 +762,7 @@ extern "C" int sr_batch_step(sr_sim* const* sims, int32_t n, int32_t max_windows
     sr_sim* s = sims[idx[k]];
     lat[k] = s->L;
     lat[k].need = s->need;
-    HIP_OR_FAIL(s0, hipMemsetAsync(s->need, 0, 2 * (size_t)((s->L.nsub + 63) / 64) * sizeof(unsigned long long), stream));
+    HIP_OR_FAIL(s0, hipMemsetAsync(s->need, 0, 2 * (size_t)need_stride(s->L.nsub), stream));
     LatRun& r = run[k];
     std::memset(&r, 0, sizeof(r));
     r.st = s->st;

@@ -96,9 +96,10 @@ struct Lattice {
   uint32_t* ckn;          // [nsub] valid checkpoints of that run
   int32_t nck;            // checkpoints per subdomain and window
   int32_t ckint;          // events + break points between checkpoints
-  unsigned long long* need;  // batched form: 2 x ceil(nsub/64) bitmaps, by
-                          // iteration parity: subdomains to run in that
-                          // iteration (set by the runs of the one before)
+  uint8_t* need;          // batched form: 2 x need_stride(nsub) bytes, by
+                          // iteration parity: 1 = the subdomain runs in
+                          // that iteration (set by the runs of the one
+                          // before, cleared by the subdomain's own run)
   SubStat* stat;          // [nsub]
   uint64_t* wlog;         // [nsub][wcap]: tick << 16 | local site
   uint32_t* wcnt;         // [nsub]
@@ -126,9 +127,10 @@ template <class LT>
 __host__ __device__ inline uint8_t* slot_at(const LT& L, int q) { return L.slot + (q & 1) * L.nsub; }
 template <class LT>
 __host__ __device__ inline uint8_t* chg_at(const LT& L, int q) { return L.chg + (q & 1) * L.nsub; }
+__host__ __device__ inline int need_stride(int nsub) { return (nsub + 63) & ~63; }
 template <class LT>
-__host__ __device__ inline unsigned long long* need_at(const LT& L, int q) {
-  return L.need + (q & 1) * ((L.nsub + 63) / 64);
+__host__ __device__ inline uint8_t* need_at(const LT& L, int q) {
+  return L.need + (q & 1) * need_stride(L.nsub);
 }
 template <class LT>
 __host__ __device__ inline int64_t* fct_at(const LT& L, int q) {

@@ -684,13 +684,17 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
     uint32_t ovf = ((nN > hcap || nS > hcap || nW > hcap || nE > hcap) ? 1u : 0u) |
                    ((nev > wcap || runaway) ? 2u : 0u);
     if (emask) fl->changed = 1u;
-    if (L.need && emask) {
-      // batched form: the neighbour facing each changed edge runs next time
-      unsigned long long* nb = need_at(L, (st.it + 1) & 1);
+    if (L.need) {
+      // batched form: this run consumed its own "runs now" mark; the
+      // neighbour facing each changed edge runs in the next iteration
+      // (plain byte stores of 0 / 1: one subdomain per byte, and the
+      // fences of the batched form order them)
+      need_at(L, st.it & 1)[d] = 0;
+      uint8_t* nb = need_at(L, (st.it + 1) & 1);
       const int facing[4] = {dn, ds, dw, de};
 #pragma unroll
       for (int e = 0; e < 4; ++e)
-        if (emask & (1u << e)) atomicOr(&nb[facing[e] >> 6], 1ull << (facing[e] & 63));
+        if (emask & (1u << e)) nb[facing[e]] = 1;
     }
     if (ovf & 1u) fl->ovf_hist = 1u;
     if (ovf & 2u) fl->ovf_log = 1u;
@@ -800,15 +804,30 @@ __device__ __forceinline__ IterFlags load_flags(const IterFlags* p) {
 
 // Wave-cooperative enqueue of the subdomains of lattice `lat` that run in
 // iteration `it`: all of them when it == 0, else those whose facing input
-// lists changed in iteration it - 1 (their bits in the need bitmap).  The
+// lists changed in iteration it - 1 (their "runs now" bytes).  The
 // others keep their lists: the slot array is copied forward and the change
 // masks cleared before anything is published.  Sets the per-shard counts
 // and shards_left before publishing any task.
 __device__ uint32_t enqueue_iteration(const BatchArgs& B, int lat, LatRun* run, CLattice& L, int it,
                                       int lane) {
   const int nsub = L.nsub;
-  const int nw = (nsub + 63) / 64;
-  unsigned long long* nb = need_at(L, it & 1);
+  const int nw = (nsub + 63) / 64;              // 64 subdomains per lane and pass
+  const uint8_t* nb = need_at(L, it & 1);
+  // the 64 "runs now" bytes of group w as a bit mask (bytes are 0 or 1)
+  auto group_mask = [&](int w) -> unsigned long long {
+    if (it == 0) {
+      const int left = nsub - w * 64;
+      return left >= 64 ? ~0ull : ((1ull << left) - 1);
+    }
+    const unsigned long long* p = reinterpret_cast<const unsigned long long*>(nb + (size_t)w * 64);
+    unsigned long long m = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const unsigned long long x = __hip_atomic_load(&p[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      m |= (((x & 0x0101010101010101ull) * 0x0102040810204080ull) >> 56) << (8 * k);
+    }
+    return m;
+  };
   if (it > 0) {
     const uint8_t* sp = slot_at(L, (it + 1) & 1);
     uint8_t* sn = slot_at(L, it & 1);
@@ -816,14 +835,8 @@ __device__ uint32_t enqueue_iteration(const BatchArgs& B, int lat, LatRun* run, 
     for (int i = lane; i < nsub; i += 64) { sn[i] = sp[i]; cn[i] = 0; }
   }
   uint32_t count = 0;
-  for (int w = 0; w < nw; w += 64) {
-    unsigned long long m = 0;
-    if (w + lane < nw) {
-      m = it == 0 ? ~0ull : __hip_atomic_load(&nb[w + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (w + lane == nw - 1 && (nsub & 63)) m &= (1ull << (nsub & 63)) - 1;
-    }
-    count += (uint32_t)__popcll(m);
-  }
+  for (int w = 0; w < nw; w += 64)
+    if (w + lane < nw) count += (uint32_t)__popcll(group_mask(w + lane));
   count = (uint32_t)wave_sum64(count);
   if (count == 0) return 0;                     // caller turns this into an error
   // task i of the iteration goes to shard (off + i) % kShards, the
@@ -847,14 +860,7 @@ __device__ uint32_t enqueue_iteration(const BatchArgs& B, int lat, LatRun* run, 
   uint32_t done_before = 0;
   for (int w0 = 0; w0 < nw; w0 += 64) {
     unsigned long long m = 0;
-    if (w0 + lane < nw) {
-      m = it == 0 ? ~0ull : __hip_atomic_load(&nb[w0 + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (w0 + lane == nw - 1 && (nsub & 63)) m &= (1ull << (nsub & 63)) - 1;
-      // reused two iterations later, when other XCDs set bits in it with
-      // device-scope atomics: clear it with one too (a plain store could sit
-      // dirty in this XCD's L2 and be written back over their bits)
-      if (it > 0) __hip_atomic_store(&nb[w0 + lane], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    if (w0 + lane < nw) m = group_mask(w0 + lane);
     const uint32_t c = (uint32_t)__popcll(m);
     const uint32_t incl = wave_incl_scan(c);
     uint32_t i = done_before + incl - c;       // task index of this lane's first bit
