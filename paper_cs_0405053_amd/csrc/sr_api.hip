@@ -234,7 +234,7 @@ static Plan plan(const sr_params& p, int64_t Wmax) {
   pl.nck = (int)std::min(32.0, std::max(4.0, std::ceil(1.5 * blk / pl.ckint) + 1.0));
   size_t nsub = (size_t)(p.Lx / p.bx) * (p.Ly / p.by), nsite = (size_t)p.Lx * p.Ly;
   pl.bytes = 2 * nsite + 2 * nsub * sizeof(Carry) + 2 * nsub * kEdges * (sizeof(uint32_t) + sizeof(int64_t)) +
-             4 * nsub + nsub * pl.nck * sizeof(Ckpt) + 2 * nsub * sizeof(uint32_t) +
+             4 * (size_t)need_stride((int)nsub) + nsub * pl.nck * sizeof(Ckpt) + 2 * nsub * sizeof(uint32_t) +
              2 * nsub * kEdges * (size_t)pl.hcap * sizeof(uint64_t) + nsub * (size_t)pl.wcap * sizeof(uint64_t) +
              2 * (size_t)need_stride((int)nsub) + nsub * sizeof(SubStat) + (p.init == SR_INIT_USER ? nsite : 0) +
              64 * 1024;
@@ -324,8 +324,8 @@ static int create_impl(const sr_params* pin, void* stream, sr_sim** out, bool in
   if (hipMalloc(&L.spins, 2 * nsite) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate lattice");
   if (hipMalloc(&L.carry, 2 * (size_t)L.nsub * sizeof(Carry)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate carry");
   if (hipMalloc(&L.hcnt, 2 * (size_t)L.nsub * kEdges * sizeof(uint32_t)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate list counts");
-  if (hipMalloc(&L.slot, 2 * (size_t)L.nsub) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate slots");
-  if (hipMalloc(&L.chg, 2 * (size_t)L.nsub) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate change flags");
+  if (hipMalloc(&L.slot, 2 * (size_t)need_stride(L.nsub)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate slots");
+  if (hipMalloc(&L.chg, 2 * (size_t)need_stride(L.nsub)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate change flags");
   if (hipMalloc(&L.fct, 2 * (size_t)L.nsub * kEdges * sizeof(int64_t)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate change ticks");
   if (hipMalloc(&L.ck, (size_t)L.nsub * L.nck * sizeof(Ckpt)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate checkpoints");
   if (hipMalloc(&L.ckn, (size_t)L.nsub * sizeof(uint32_t)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate checkpoint counts");

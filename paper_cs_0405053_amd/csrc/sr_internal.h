@@ -86,10 +86,11 @@ struct Lattice {
   Carry* carry;           // 2 x nsub: by window parity
   uint64_t* hist;         // 2 x [nsub][4][hcap]: two list slots per subdomain
   uint32_t* hcnt;         // 2 x [nsub][4]: list lengths, per slot
-  uint8_t* slot;          // 2 x nsub: slot holding a subdomain's latest lists,
-                          // by iteration parity
-  uint8_t* chg;           // 2 x nsub: which of a subdomain's lists (bit per edge
-                          // N, S, W, E) changed in that iteration, by parity
+  uint8_t* slot;          // 2 x need_stride(nsub): slot holding a subdomain's
+                          // latest lists, by iteration parity
+  uint8_t* chg;           // 2 x need_stride(nsub): which of a subdomain's lists
+                          // (bit per edge N, S, W, E) changed in that
+                          // iteration, by parity
   int64_t* fct;           // 2 x [nsub][4]: per slot, first tick at which a list
                           // differs from its previous version (kTickInf: same)
   Ckpt* ck;               // [nsub][nck] checkpoints of each subdomain's last run
@@ -123,11 +124,13 @@ template <class LT>
 __host__ __device__ inline uint32_t* hcnt_at(const LT& L, int q) {
   return L.hcnt + (q & 1) * (L.nsub * kEdges);
 }
-template <class LT>
-__host__ __device__ inline uint8_t* slot_at(const LT& L, int q) { return L.slot + (q & 1) * L.nsub; }
-template <class LT>
-__host__ __device__ inline uint8_t* chg_at(const LT& L, int q) { return L.chg + (q & 1) * L.nsub; }
+// Per-subdomain byte arrays (slot, change mask, run marks) are padded to a
+// multiple of 64 subdomains, so that they can be copied 16 bytes at a time.
 __host__ __device__ inline int need_stride(int nsub) { return (nsub + 63) & ~63; }
+template <class LT>
+__host__ __device__ inline uint8_t* slot_at(const LT& L, int q) { return L.slot + (q & 1) * need_stride(L.nsub); }
+template <class LT>
+__host__ __device__ inline uint8_t* chg_at(const LT& L, int q) { return L.chg + (q & 1) * need_stride(L.nsub); }
 template <class LT>
 __host__ __device__ inline uint8_t* need_at(const LT& L, int q) {
   return L.need + (q & 1) * need_stride(L.nsub);

@@ -779,27 +779,30 @@ __global__ void clear_flags_kernel(IterFlags* f, int n) {
 // in scalar registers or reload them instead of pinning ~100 values.
 typedef const __attribute__((address_space(4))) Lattice CLattice;
 
-// Mutable per-lattice state read at a wave-uniform address, field by field
-// through readfirstlane so that it lives in scalar registers.
-__device__ __forceinline__ int32_t u32s(const int32_t& x) { return __builtin_amdgcn_readfirstlane(x); }
-__device__ __forceinline__ uint32_t u32s(const uint32_t& x) {
-  return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+// The 128-byte per-lattice record, one 32-bit word per lane (lanes 0..31),
+// fetched with one load instead of one dependent load per field.
+static_assert(sizeof(LatRun) == 128, "LatRun is read as 32 words");
+struct RunView {
+  uint32_t w;
+  __device__ __forceinline__ uint32_t u32(size_t off) const { return rdl(w, (int)(off / 4)); }
+  __device__ __forceinline__ int64_t i64(size_t off) const {
+    return (int64_t)(((uint64_t)rdl(w, (int)(off / 4) + 1) << 32) | rdl(w, (int)(off / 4)));
+  }
+};
+__device__ __forceinline__ RunView load_run(const LatRun* run, int lane) {
+  RunView v;
+  v.w = lane < 32 ? reinterpret_cast<const uint32_t*>(run)[lane] : 0u;
+  return v;
 }
-__device__ __forceinline__ int64_t u64s(const int64_t& x) {
-  uint64_t v = (uint64_t)x;
-  return (int64_t)(((uint64_t)u32s((uint32_t)(v >> 32)) << 32) | u32s((uint32_t)v));
-}
-__device__ __forceinline__ Step load_step(const Step* p) {
+__device__ __forceinline__ Step step_of(const RunView& v) {
   Step st;
-  st.t_c = u64s(p->t_c); st.t_end = u64s(p->t_end);
-  st.wp = u32s(p->wp); st.it = u32s(p->it); st.fi = u32s(p->fi); st.pad = 0;
+  st.t_c = v.i64(offsetof(LatRun, st) + offsetof(Step, t_c));
+  st.t_end = v.i64(offsetof(LatRun, st) + offsetof(Step, t_end));
+  st.wp = (int32_t)v.u32(offsetof(LatRun, st) + offsetof(Step, wp));
+  st.it = (int32_t)v.u32(offsetof(LatRun, st) + offsetof(Step, it));
+  st.fi = (int32_t)v.u32(offsetof(LatRun, st) + offsetof(Step, fi));
+  st.pad = 0;
   return st;
-}
-__device__ __forceinline__ IterFlags load_flags(const IterFlags* p) {
-  IterFlags f;
-  f.changed = u32s(p->changed); f.ovf_hist = u32s(p->ovf_hist); f.ovf_log = u32s(p->ovf_log);
-  f.pad = 0;
-  return f;
 }
 
 // Wave-cooperative enqueue of the subdomains of lattice `lat` that run in
@@ -813,30 +816,50 @@ __device__ uint32_t enqueue_iteration(const BatchArgs& B, int lat, LatRun* run, 
   const int nsub = L.nsub;
   const int nw = (nsub + 63) / 64;              // 64 subdomains per lane and pass
   const uint8_t* nb = need_at(L, it & 1);
-  // the 64 "runs now" bytes of group w as a bit mask (bytes are 0 or 1)
+  // the 64 "runs now" bytes of group w as a bit mask (bytes are 0 or 1):
+  // four 16-byte loads, then the gather
   auto group_mask = [&](int w) -> unsigned long long {
     if (it == 0) {
       const int left = nsub - w * 64;
       return left >= 64 ? ~0ull : ((1ull << left) - 1);
     }
-    const unsigned long long* p = reinterpret_cast<const unsigned long long*>(nb + (size_t)w * 64);
+    const uint4* p = reinterpret_cast<const uint4*>(nb + (size_t)w * 64);
+    uint4 x[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x[k] = p[k];
     unsigned long long m = 0;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const unsigned long long x = __hip_atomic_load(&p[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      m |= (((x & 0x0101010101010101ull) * 0x0102040810204080ull) >> 56) << (8 * k);
+    for (int k = 0; k < 4; ++k) {
+      const unsigned long long lo = ((unsigned long long)x[k].y << 32) | x[k].x;
+      const unsigned long long hi = ((unsigned long long)x[k].w << 32) | x[k].z;
+      m |= (((lo & 0x0101010101010101ull) * 0x0102040810204080ull) >> 56) << (16 * k);
+      m |= (((hi & 0x0101010101010101ull) * 0x0102040810204080ull) >> 56) << (16 * k + 8);
     }
     return m;
   };
   if (it > 0) {
-    const uint8_t* sp = slot_at(L, (it + 1) & 1);
-    uint8_t* sn = slot_at(L, it & 1);
-    uint8_t* cn = chg_at(L, it & 1);
-    for (int i = lane; i < nsub; i += 64) { sn[i] = sp[i]; cn[i] = 0; }
+    // subdomains that do not run keep their lists: carry their slot
+    // forward and clear the change masks, 16 bytes per lane and step
+    const uint4* sp = reinterpret_cast<const uint4*>(slot_at(L, (it + 1) & 1));
+    uint4* sn = reinterpret_cast<uint4*>(slot_at(L, it & 1));
+    uint4* cn = reinterpret_cast<uint4*>(chg_at(L, it & 1));
+    const int n16 = need_stride(nsub) / 16;
+    const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll 4
+    for (int i = lane; i < n16; i += 64) {
+      sn[i] = sp[i];
+      cn[i] = zero;
+    }
   }
   uint32_t count = 0;
-  for (int w = 0; w < nw; w += 64)
-    if (w + lane < nw) count += (uint32_t)__popcll(group_mask(w + lane));
+  unsigned long long m_first = 0;               // the first pass's masks, kept
+  for (int w = 0; w < nw; w += 64) {
+    if (w + lane < nw) {
+      const unsigned long long m = group_mask(w + lane);
+      if (w == 0) m_first = m;
+      count += (uint32_t)__popcll(m);
+    }
+  }
   count = (uint32_t)wave_sum64(count);
   if (count == 0) return 0;                     // caller turns this into an error
   // task i of the iteration goes to shard (off + i) % kShards, the
@@ -856,11 +879,27 @@ __device__ uint32_t enqueue_iteration(const BatchArgs& B, int lat, LatRun* run, 
 #pragma unroll
   for (int k = 0; k < kShards; ++k) bases[k] = rdl64(sbase, k);
   const size_t qn = (size_t)B.qmask + 1;
-  // lane-major walk: word w of the bitmap, its set bits in ascending order
+  if (it == 0) {
+    // every subdomain runs: task i is subdomain i, in shard (off + i) mod
+    // kShards at position i / kShards; 64 is a multiple of kShards, so a
+    // lane's shard is the same in every round
+    const int sh = (off + lane) % kShards;
+    unsigned long long base = bases[0];
+#pragma unroll
+    for (int k = 1; k < kShards; ++k) base = sh == k ? bases[k] : base;
+    unsigned long long* qs = B.q + (size_t)sh * qn;
+    for (int d = lane; d < nsub; d += 64) {
+      const unsigned long long at = base + (unsigned)d / kShards;
+      __hip_atomic_store(&qs[at & B.qmask], ((at + 1) << 32) | ((unsigned long long)lat << 20) | (unsigned)d,
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return count;
+  }
+  // lane-major walk: 64 subdomains per lane, set marks in ascending order
   uint32_t done_before = 0;
   for (int w0 = 0; w0 < nw; w0 += 64) {
     unsigned long long m = 0;
-    if (w0 + lane < nw) m = group_mask(w0 + lane);
+    if (w0 + lane < nw) m = w0 == 0 ? m_first : group_mask(w0 + lane);
     const uint32_t c = (uint32_t)__popcll(m);
     const uint32_t incl = wave_incl_scan(c);
     uint32_t i = done_before + incl - c;       // task index of this lane's first bit
@@ -889,16 +928,25 @@ __device__ void decide(const BatchArgs& B, int lat, int lane) {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   LatRun* run = &B.run[lat];
   CLattice& L = ((CLattice*)B.lat)[lat];
-  const IterFlags f = load_flags(&run->fl);
-  Step st = load_step(&run->st);
+  const RunView rv = load_run(run, lane);
+  IterFlags f;
+  f.changed = rv.u32(offsetof(LatRun, fl) + offsetof(IterFlags, changed));
+  f.ovf_hist = rv.u32(offsetof(LatRun, fl) + offsetof(IterFlags, ovf_hist));
+  f.ovf_log = rv.u32(offsetof(LatRun, fl) + offsetof(IterFlags, ovf_log));
+  f.pad = 0;
+  Step st = step_of(rv);
+  const int32_t max_iters = (int32_t)rv.u32(offsetof(LatRun, max_iters));
+  const int32_t tune = (int32_t)rv.u32(offsetof(LatRun, tune));
+  const int32_t win_budget = (int32_t)rv.u32(offsetof(LatRun, win_budget));
+  const int64_t H = rv.i64(offsetof(LatRun, H));
   bool finish = false;
-  if (lane == 0) run->iterations += 1;
+  if (lane == 0) run->iterations = rv.i64(offsetof(LatRun, iterations)) + 1;
   int next_it = -1;
   if (f.ovf_hist || f.ovf_log) {
     if (lane == 0) run->status = kOverflow;
     finish = true;
   } else if (f.changed) {
-    if (st.it + 1 >= run->max_iters) {
+    if (st.it + 1 >= max_iters) {
       if (lane == 0) run->status = kNoConv;
       finish = true;
     } else {
@@ -908,25 +956,25 @@ __device__ void decide(const BatchArgs& B, int lat, int lane) {
     // converged: the working outputs become committed (parity flip)
     st.wp ^= 1;
     st.t_c = st.t_end;
-    const int64_t wins = u64s(run->windows) + 1;     // read by every lane before the update
+    const int64_t wins = rv.i64(offsetof(LatRun, windows)) + 1;
     if (lane == 0) {
       run->windows = wins;
       run->last_g = st.it + 1;
     }
-    int64_t W = u64s(run->W);
-    if (run->tune) {
-      W = tune_window(W, st.it + 1, run->Wmin, run->Wmax);
+    int64_t W = rv.i64(offsetof(LatRun, W));
+    if (tune) {
+      W = tune_window(W, st.it + 1, rv.i64(offsetof(LatRun, Wmin)), rv.i64(offsetof(LatRun, Wmax)));
       if (lane == 0) run->W = W;
     }
-    if (st.t_c >= run->H) {
+    if (st.t_c >= H) {
       if (lane == 0) { run->status = kDone; run->st = st; }
       finish = true;
-    } else if (run->win_budget >= 0 && wins >= run->win_budget) {
+    } else if (win_budget >= 0 && wins >= win_budget) {
       // this launch's share of windows is done: pause at committed time
       if (lane == 0) { run->status = kPaused; run->st = st; }
       finish = true;
     } else {
-      st.t_end = min64(st.t_c + W, run->H);
+      st.t_end = min64(st.t_c + W, H);
       next_it = 0;
     }
   }
@@ -954,8 +1002,11 @@ __device__ void decide(const BatchArgs& B, int lat, int lane) {
 constexpr uint32_t kSpinBudget = 20u << 20;
 
 // Wave w serves shard w % kShards (consecutive workgroups go to different
-// XCDs, so each shard's counters are hit mostly from one XCD).  Per task: one
-// ticket, wait for its slot, acquire, relax, release, count down.
+// XCDs, so each shard's counters are hit mostly from one XCD).  Per task:
+// wait for the slot of the ticket held, acquire, relax, release, count the
+// task down while taking the next ticket.  A held ticket whose task is not
+// produced yet blocks no one: tasks are produced by deciders, and a wave
+// finishes its current task before it waits.
 __global__ __launch_bounds__(64) void batch_kernel(BatchArgs B) {
   extern __shared__ int8_t tile[];
   const int lane = lane_id();
@@ -963,10 +1014,10 @@ __global__ __launch_bounds__(64) void batch_kernel(BatchArgs B) {
   const int g = (int)(blockIdx.x % kShards);
   ShardCtr* sc = &B.ctr->sh[g];
   const unsigned long long* qg = B.q + (size_t)g * ((size_t)B.qmask + 1);
+  unsigned long long t = 0;
+  if (lane == 0) t = atomicAdd(&sc->head, 1ull);
+  t = ((uint64_t)rdl((uint32_t)(t >> 32), 0) << 32) | rdl((uint32_t)t, 0);
   for (;;) {
-    unsigned long long t = 0;
-    if (lane == 0) t = atomicAdd(&sc->head, 1ull);
-    t = ((uint64_t)rdl((uint32_t)(t >> 32), 0) << 32) | rdl((uint32_t)t, 0);
     const uint32_t want = (uint32_t)(t + 1);
     unsigned long long v;
     uint32_t spins = 0;
@@ -988,15 +1039,20 @@ __global__ __launch_bounds__(64) void batch_kernel(BatchArgs B) {
     const int d = (int)(pay & 0xFFFFF);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     LatRun* run = &B.run[lat];
-    const Step st = load_step(&run->st);
+    const Step st = step_of(load_run(run, lane));
     relax_subdomain(lats[lat], st, d, tile, &run->fl);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // count this task down and take the next ticket: both memory-side
+    // atomics are in flight together
     int last = 0;
+    unsigned long long tn = 0;
     if (lane == 0) {
-      if (atomicSub(&B.rem[(size_t)lat * kShards + g].n, 1) == 1)
-        last = (atomicSub(&run->shards_left, 1) == 1);
+      const int32_t left = atomicSub(&B.rem[(size_t)lat * kShards + g].n, 1);
+      tn = atomicAdd(&sc->head, 1ull);
+      if (left == 1) last = (atomicSub(&run->shards_left, 1) == 1);
     }
     last = (int)rdl((uint32_t)last, 0);
+    t = ((uint64_t)rdl((uint32_t)(tn >> 32), 0) << 32) | rdl((uint32_t)tn, 0);
     if (last) decide(B, lat, lane);
   }
 }
