@@ -52,6 +52,8 @@ def main():
     ap.add_argument("--no-medium", action="store_true",
                     help="skip the headline leg (profiling the other legs alone)")
     ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--sweep-horizon", type=float, default=200.0)
     ap.add_argument("--temps", default=None, help="comma list, default all three")
     ap.add_argument("--horizon", type=float, default=100.0,
                     help="shorter horizons only for profiler runs")
@@ -79,6 +81,8 @@ def main():
             side["batched_vs_plain"] = bench_batch(sr, W, stream, torch)
         if not args.no_serve:
             side["serving"] = bench_serve(sr, W, stream, n=args.serve_requests)
+        if not args.no_sweep:
+            side["large_window_sweep"] = bench_window_sweep(sr, W, stream, torch, args.sweep_horizon)
         print(json.dumps(side), flush=True)
         return
     temps = W.MEDIUM_TEMPS if not args.temps else tuple(float(x) for x in args.temps.split(","))
@@ -202,6 +206,11 @@ def main():
             line["serving"] = bench_serve(sr, W, stream, n=args.serve_requests)
         except Exception as e:
             line["serving"] = {"error": repr(e)}
+    if not args.no_sweep:
+        try:
+            line["large_window_sweep"] = bench_window_sweep(sr, W, stream, torch, args.sweep_horizon)
+        except Exception as e:
+            line["large_window_sweep"] = {"error": repr(e)}
 
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(sr, W, stream, temps)
@@ -255,6 +264,40 @@ def bench_batch(sr, W, stream, torch, n=512, horizon=50.0):
             "plain_flips_per_s": round(flips / t_plain, 1),
             "batched_flips_per_s": round(flips_b / t_batch, 1),
             "speedup": round(t_plain / t_batch, 3), "bit_exact": bool(same and flips == flips_b)}
+
+
+def bench_window_sweep(sr, W, stream, torch, horizon):
+    """The 4096x4096 low-temperature lattice (all up, T = 1, h = 0.05, 16384
+    subdomains of 32x32) at three step sizes: committed flips/s and
+    iterations per window for each, and the final state, which must be the
+    same for every window (the trajectory does not depend on the step)."""
+    import numpy as np
+    out, ref = {}, None
+    same = True
+    for w in W.LARGE_WINDOWS:
+        s = sr.Sim(dict(W.large(window=w, horizon=horizon), log_mode="digest"), stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = s.run()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        o = s.observables()
+        dg = s.digests()[0].copy()
+        if ref is None:
+            ref = (dg, o["M"], o["flips"])
+        else:
+            same &= bool(np.array_equal(dg, ref[0]) and o["M"] == ref[1] and o["flips"] == ref[2])
+        out[f"window_{w:g}"] = {"committed_flips_per_s": round(o["flips"] / dt, 1), "seconds": round(dt, 3),
+                                "windows": int(o["windows"]), "iters_per_window": round(float(g.mean()), 3),
+                                "processed_per_committed": round(o["events_processed"] / max(o["flips"], 1), 3),
+                                "avg_launch_us": round(1e3 * o["relax_ms"] / max(o["relax_launches"], 1), 2)}
+        log(f"window sweep W={w}: {o['flips']} flips in {dt:.2f}s")
+        s.close()
+    out["workload"] = (f"4096x4096 periodic, J=1, h=0.05, T=1.0, all +1 start, 16384 subdomains of 32x32, "
+                       f"horizon {horizon:g}, windows {list(W.LARGE_WINDOWS)}")
+    out["committed_flips"] = int(ref[2])
+    out["identical_across_windows"] = bool(same)
+    return out
 
 
 def bench_serve(sr, W, stream, n=64, rate=200.0, budget_gib=96, wpr=8, n_check=3):
