@@ -193,7 +193,7 @@ int sr_batch_step(sr_sim* const* sims, int32_t n, int32_t max_windows, void* hip
  * Sec. 5, clamped to [1/8, 2].  A simulation created with window = 0 then
  * adapts its step size after every committed window from the measured
  * iterations g (Sec. 4 box: a step size is chosen at each step), aiming at
- * about 10 iterations per window; the trajectory does not depend on it. */
+ * about 16 iterations per window; the trajectory does not depend on it. */
 int sr_tune(const sr_params* p, int32_t* bx, int32_t* by, double* window);
 
 /* ---- serving: continuous batching of simulation requests ----
