@@ -1073,27 +1073,34 @@ __global__ void fill_kernel(int8_t* s, int64_t n, int8_t v) {
     s[i] = v;
 }
 
-// out[0] += sum s, out[1] += sum s (s_right + s_down)
+// out[0] += sum s, out[1] += sum s (s_right + s_down).  Blocks stride over
+// rows (no per-element index division); each block reduces in LDS and adds
+// its two totals once (device-scope atomics are served at the memory side,
+// so one per wave on a single address would serialise the whole grid).
 __global__ __launch_bounds__(256) void observables_kernel(const int8_t* s, int Lx, int Ly,
                                                           unsigned long long* out) {
-  int64_t n = (int64_t)Lx * Ly;
+  __shared__ long long red[2][4];
   long long m = 0, b = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    int y = (int)(i / Lx), x = (int)(i - (int64_t)y * Lx);
-    int v = s[i];
-    int r = s[(int64_t)y * Lx + (x + 1 == Lx ? 0 : x + 1)];
-    int dn = s[(int64_t)(y + 1 == Ly ? 0 : y + 1) * Lx + x];
-    m += v;
-    b += v * (r + dn);
+  for (int y = blockIdx.x; y < Ly; y += gridDim.x) {
+    const int8_t* row = s + (int64_t)y * Lx;
+    const int8_t* below = s + (int64_t)(y + 1 == Ly ? 0 : y + 1) * Lx;
+    for (int x = threadIdx.x; x < Lx; x += blockDim.x) {
+      const int v = row[x];
+      const int r = row[x + 1 == Lx ? 0 : x + 1];
+      m += v;
+      b += v * (r + below[x]);
+    }
   }
   for (int off = 32; off >= 1; off >>= 1) {
     m += __shfl_xor(m, off, 64);
     b += __shfl_xor(b, off, 64);
   }
-  if ((threadIdx.x & 63) == 0) {
-    atomicAdd(&out[0], (unsigned long long)m);
-    atomicAdd(&out[1], (unsigned long long)b);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { red[0][w] = m; red[1][w] = b; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicAdd(&out[0], (unsigned long long)(red[0][0] + red[0][1] + red[0][2] + red[0][3]));
+    atomicAdd(&out[1], (unsigned long long)(red[1][0] + red[1][1] + red[1][2] + red[1][3]));
   }
 }
 
@@ -1175,9 +1182,7 @@ hipError_t launch_fill(int8_t* s, int64_t n, int8_t v, hipStream_t stream) {
 
 hipError_t launch_observables(const int8_t* s, int Lx, int Ly, unsigned long long* out,
                               hipStream_t stream) {
-  int64_t n = (int64_t)Lx * Ly;
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
+  const int blocks = Ly < 512 ? Ly : 512;      // one or more rows per block
   hipLaunchKernelGGL(observables_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, s, Lx, Ly,
                      out);
   return hipGetLastError();

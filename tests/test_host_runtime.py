@@ -42,16 +42,16 @@ def run(exe, scenario, **env):
 
 
 def test_tuned_window_count_exceeds_first_estimate(drive):
-    # windows needing 20 iterations shrink the tuned step size, so far more
+    # windows needing 40 iterations shrink the tuned step size, so far more
     # windows are committed than the first window predicts; the iteration
     # counts must still land only in caller-bounded buffers
-    out = run(drive, "tuned", SR_MOCK_G=20)
+    out = run(drive, "tuned", SR_MOCK_G=40)
     assert "windows" in out
 
 
 @pytest.mark.parametrize("graphs", ["0", "1"])
 def test_tuned_window_plain_and_graph_paths(drive, graphs):
-    run(drive, "tuned", SR_MOCK_G=13, SR_NO_GRAPHS=graphs)
+    run(drive, "tuned", SR_MOCK_G=48, SR_NO_GRAPHS=graphs)
 
 
 @pytest.mark.parametrize("g", [1, 7])
