@@ -262,11 +262,23 @@ __host__ __device__ inline size_t relax_lds_bytes(int bx, int by, int hcap) {
 // ------------------------------------------------------------ relaxation
 // One subdomain (this wave) over one window, one iteration (Sec. 4 box, step
 // (a) for one PE; Sec. 5 for the Ising specifics).
-template <class LT>
+// log2 of the sites per lane of a bx x by block (a power of two).
+constexpr int lane_shift(int nblk) {
+  int sh = 0;
+  while ((1 << sh) * 64 < nblk) sh++;
+  return sh;
+}
+
+// BX, BY > 0: the block shape is a compile-time constant (the common shapes
+// get their own instantiation: fewer live scalar registers and constant
+// index arithmetic); 0: read from the lattice.
+template <int BX, int BY, class LT>
 __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int d,
                                                 int8_t* lds, IterFlags* fl) {
+  static_assert((BX == 0) == (BY == 0), "both or neither block sides fixed");
   const int lane = lane_id();
-  const int bx = L.bx, by = L.by, sh = L.sshift, S = 1 << sh;
+  const int bx = BX ? BX : L.bx, by = BY ? BY : L.by;
+  const int sh = BX ? lane_shift(BX * BY) : L.sshift, S = 1 << sh;
   const int nbx = L.nbx, nby = L.nby;
   const int cx = d % nbx, cy = d / nbx;
   const int x0 = cx * bx, y0 = cy * by;
@@ -718,6 +730,7 @@ __device__ __forceinline__ bool inputs_changed(const LT& L, int it, int d) {
   return need;
 }
 
+template <int BX, int BY>
 __global__ __launch_bounds__(64) void relax_kernel(Lattice L, Step st) {
   extern __shared__ int8_t tile[];
   const int d = blockIdx.x;
@@ -736,12 +749,13 @@ __global__ __launch_bounds__(64) void relax_kernel(Lattice L, Step st) {
     }
     return;
   }
-  relax_subdomain(L, st, d, tile, L.flags + st.fi);
+  relax_subdomain<BX, BY>(L, st, d, tile, L.flags + st.fi);
 }
 
 // Graph form of the plain iteration: the window descriptor lives in device
 // memory (written by the host before each replay) and node i of the graph is
 // iteration st.it + i.
+template <int BX, int BY>
 __global__ __launch_bounds__(64) void relax_graph_kernel(Lattice L, const Step* stp, int i) {
   extern __shared__ int8_t tile[];
   const int d = blockIdx.x;
@@ -761,7 +775,7 @@ __global__ __launch_bounds__(64) void relax_graph_kernel(Lattice L, const Step* 
     }
     return;
   }
-  relax_subdomain(L, st, d, tile, L.flags + i);
+  relax_subdomain<BX, BY>(L, st, d, tile, L.flags + i);
 }
 
 // Clears the first n iteration flags (a kernel, so that graphs hold no
@@ -1040,7 +1054,7 @@ __global__ __launch_bounds__(64) void batch_kernel(BatchArgs B) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     LatRun* run = &B.run[lat];
     const Step st = step_of(load_run(run, lane));
-    relax_subdomain(lats[lat], st, d, tile, &run->fl);
+    relax_subdomain<0, 0>(lats[lat], st, d, tile, &run->fl);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     // count this task down and take the next ticket: both memory-side
     // atomics are in flight together
@@ -1107,7 +1121,12 @@ __global__ __launch_bounds__(256) void observables_kernel(const int8_t* s, int L
 // ------------------------------------------------------------ launchers
 hipError_t launch_relax(const Lattice& L, const Step& st, hipStream_t stream) {
   size_t lds = relax_lds_bytes(L.bx, L.by, L.hcap);
-  hipLaunchKernelGGL(relax_kernel, dim3(L.nsub), dim3(64), lds, stream, L, st);
+  if (L.bx == 16 && L.by == 16)
+    hipLaunchKernelGGL((relax_kernel<16, 16>), dim3(L.nsub), dim3(64), lds, stream, L, st);
+  else if (L.bx == 32 && L.by == 32)
+    hipLaunchKernelGGL((relax_kernel<32, 32>), dim3(L.nsub), dim3(64), lds, stream, L, st);
+  else
+    hipLaunchKernelGGL((relax_kernel<0, 0>), dim3(L.nsub), dim3(64), lds, stream, L, st);
   return hipGetLastError();
 }
 
@@ -1138,7 +1157,9 @@ hipError_t build_window_graph(const Lattice& L, const Step* dstep, int k, hipGra
     idx[i] = i;
     void* rargs[] = {&Lc, &sp, &idx[i]};
     hipKernelNodeParams rp = {};
-    rp.func = (void*)relax_graph_kernel;
+    rp.func = (L.bx == 16 && L.by == 16)   ? (void*)relax_graph_kernel<16, 16>
+              : (L.bx == 32 && L.by == 32) ? (void*)relax_graph_kernel<32, 32>
+                                           : (void*)relax_graph_kernel<0, 0>;
     rp.gridDim = dim3(L.nsub);
     rp.blockDim = dim3(64);
     rp.sharedMemBytes = (unsigned)lds;
