@@ -127,15 +127,21 @@ __device__ __forceinline__ void draw_chunk(uint32_t k0, uint32_t k1, uint64_t j0
 
 // ------------------------------------------------------------ integer time
 // floor(n / d) and ceil(n / d) for d >= 1, exact when the quotient is below
-// 2^50 (a double estimate, then one correction step); larger quotients are
-// reported as 2^50, which callers treat as "beyond any horizon".
+// 2^50: a double estimate from the hardware reciprocal refined by one Newton
+// step (no IEEE division sequence), then exact integer correction.  Larger
+// quotients are reported as 2^50, which callers treat as "beyond any
+// horizon" (horizons are below 2^46 ticks, so an estimate near that bound
+// that lands on either side gives the same behaviour).
 __device__ __forceinline__ uint64_t udiv_floor(uint64_t n, uint64_t d, uint64_t* rem_nonzero) {
-  double qd = (double)n / (double)d;
+  const double dd = (double)d;
+  double r = __builtin_amdgcn_rcp(dd);
+  r = __builtin_fma(r, __builtin_fma(-dd, r, 1.0), r);
+  const double qd = (double)n * r;
   if (qd >= 1125899906842624.0) { *rem_nonzero = 1; return 1ull << 50; }
   uint64_t q = (uint64_t)qd;
   uint64_t p = q * d;
-  if (p > n) { q -= 1; p -= d; }
-  else if (n - p >= d) { q += 1; p += d; }
+  while (p > n) { q -= 1; p -= d; }
+  while (n - p >= d) { q += 1; p += d; }
   *rem_nonzero = (n != p);
   return q;
 }
@@ -581,12 +587,39 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
       const int ly = v / bx, lx = v - ly * bx;
       const int kv = (int)((rdl64(cls, v >> sh) >> ((v & (S - 1)) * 4)) & 15);
       const bool now_up = kv >= 5;
-      change(v, now_up ? -5 : 5);
       const int dup = now_up ? 1 : -1;
-      if (lx > 0) change(v - 1, dup); else if (wrapx) change(v + bx - 1, dup);
-      if (lx < bx - 1) change(v + 1, dup); else if (wrapx) change(v - bx + 1, dup);
-      if (ly > 0) change(v - bx, dup); else if (wrapy) change(v + (by - 1) * bx, dup);
-      if (ly < by - 1) change(v + bx, dup); else if (wrapy) change(v - (by - 1) * bx, dup);
+      if ((bx >= 3 || !wrapx) && (by >= 3 || !wrapy)) {
+        // the flipped site and its in-block neighbours are five distinct
+        // sites: read every old class from the words before the flip and
+        // apply all the moves at once (no chain through the class words)
+        const int nbr[4] = {lx > 0 ? v - 1 : (wrapx ? v + bx - 1 : -1),
+                            lx < bx - 1 ? v + 1 : (wrapx ? v - bx + 1 : -1),
+                            ly > 0 ? v - bx : (wrapy ? v + (by - 1) * bx : -1),
+                            ly < by - 1 ? v + bx : (wrapy ? v - (by - 1) * bx : -1)};
+        const int dv = now_up ? -5 : 5;
+        uint64_t add = lane == (v >> sh) ? (uint64_t)(int64_t)dv << ((v & (S - 1)) * 4) : 0ull;
+        uint32_t inc = (uint32_t)(lane == kv + dv), dec = (uint32_t)(lane == kv);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int u = nbr[q];
+          if (u < 0) continue;
+          const int o = u >> sh, sl = (u & (S - 1)) * 4;
+          const int a = (int)((rdl64(cls, o) >> sl) & 15);
+          add += lane == o ? (uint64_t)(int64_t)dup << sl : 0ull;
+          inc += (uint32_t)(lane == a + dup);
+          dec += (uint32_t)(lane == a);
+        }
+        cls += add;
+        ncnt += inc - dec;
+      } else {
+        // a 2-wide block wrapping onto itself: both horizontal (or vertical)
+        // neighbours are the same site, so the moves must chain
+        change(v, now_up ? -5 : 5);
+        if (lx > 0) change(v - 1, dup); else if (wrapx) change(v + bx - 1, dup);
+        if (lx < bx - 1) change(v + 1, dup); else if (wrapx) change(v - bx + 1, dup);
+        if (ly > 0) change(v - bx, dup); else if (wrapy) change(v + (by - 1) * bx, dup);
+        if (ly < by - 1) change(v + bx, dup); else if (wrapy) change(v - (by - 1) * bx, dup);
+      }
       // record
       const uint64_t tk = (uint64_t)t << kPosBits;
       if (lane == (nev & 63)) lbuf = tk | (uint64_t)v;
