@@ -265,6 +265,11 @@ __host__ __device__ inline size_t relax_lds_bytes(int bx, int by, int hcap) {
   return (b + 15) & ~(size_t)15;
 }
 
+// Per-lattice descriptors are read through the constant address space: they
+// do not change while the kernel runs, so the compiler may keep their fields
+// in scalar registers or reload them instead of pinning ~100 values.
+typedef const __attribute__((address_space(4))) Lattice CLattice;
+
 // ------------------------------------------------------------ relaxation
 // One subdomain (this wave) over one window, one iteration (Sec. 4 box, step
 // (a) for one PE; Sec. 5 for the Ising specifics).
@@ -782,7 +787,9 @@ __global__ __launch_bounds__(64) void relax_kernel(Lattice L, Step st) {
     }
     return;
   }
-  relax_subdomain<BX, BY>(L, st, d, tile, L.flags + st.fi);
+  // the descriptor is read in place from the kernel arguments (constant
+  // address space), so rarely used fields need not stay in registers
+  relax_subdomain<BX, BY>(*(CLattice*)__builtin_amdgcn_kernarg_segment_ptr(), st, d, tile, L.flags + st.fi);
 }
 
 // Graph form of the plain iteration: the window descriptor lives in device
@@ -808,7 +815,7 @@ __global__ __launch_bounds__(64) void relax_graph_kernel(Lattice L, const Step* 
     }
     return;
   }
-  relax_subdomain<BX, BY>(L, st, d, tile, L.flags + i);
+  relax_subdomain<BX, BY>(*(CLattice*)__builtin_amdgcn_kernarg_segment_ptr(), st, d, tile, L.flags + i);
 }
 
 // Clears the first n iteration flags (a kernel, so that graphs hold no
@@ -821,10 +828,6 @@ __global__ void clear_flags_kernel(IterFlags* f, int n) {
 }
 
 // ------------------------------------------------------------ batched form
-// Per-lattice descriptors are read through the constant address space: they
-// do not change while the kernel runs, so the compiler may keep their fields
-// in scalar registers or reload them instead of pinning ~100 values.
-typedef const __attribute__((address_space(4))) Lattice CLattice;
 
 // The 128-byte per-lattice record, one 32-bit word per lane (lanes 0..31),
 // fetched with one load instead of one dependent load per field.
