@@ -87,36 +87,50 @@ def main():
         return
     temps = W.MEDIUM_TEMPS if not args.temps else tuple(float(x) for x in args.temps.split(","))
     ps = [W.medium(T=T, horizon=args.horizon) for T in temps]
-    sims = [sr.Sim(dict(p, log_mode="digest"), stream=stream) for p in ps]
+    # one HIP stream per lattice (default priority); the plain form's window
+    # loops of the lattices run concurrently from one host thread each
+    streams = [torch.cuda.Stream() for _ in ps]
+    sims = [sr.Sim(dict(p, log_mode="digest"), stream=st) for p, st in zip(ps, streams)]
+    from concurrent.futures import ThreadPoolExecutor
+    pool = ThreadPoolExecutor(max_workers=len(sims))
 
-    def step():
-        out = []
-        for s in sims:
-            s.reset()
-            g = s.run()
-            o = s.observables()
-            out.append((g, o, s.digests()[0]))
-        return out
+    def run_one(s):
+        s.reset()
+        g = s.run()
+        o = s.observables()
+        return (g, o, s.digests()[0])
 
-    for i in range(args.warmup):
-        log(f"warmup step {i}")
-        ref = step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    results = []
-    for i in range(args.steps):
-        results.append(step())
-        log(f"timed step {i} done")
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    dt = (t1 - t0) / max(args.steps, 1)
+    def step():                       # the lattices concurrently (the headline)
+        return list(pool.map(run_one, sims))
+
+    def step_sequential():            # one lattice after the other
+        return [run_one(s) for s in sims]
+
+    def timed(fn, what):
+        for i in range(args.warmup):
+            log(f"warmup {what} step {i}")
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = []
+        for i in range(args.steps):
+            res.append(fn())
+            log(f"timed {what} step {i} done")
+        torch.cuda.synchronize()
+        return res, (time.perf_counter() - t0) / max(args.steps, 1)
+
+    results, dt = timed(step, "concurrent")
+    results_seq, dt_seq = timed(step_sequential, "sequential")
+    seq_same = all(np.array_equal(a[2], b[2]) for a, b in zip(results_seq[-1], results[-1]))
 
     flips = sum(o["flips"] for g, o, d in results[-1])
     processed = sum(o["events_processed"] for g, o, d in results[-1])
     gs = np.concatenate([g for g, o, d in results[-1]])
-    launches = sum(o["relax_launches"] for g, o, d in results[-1])
-    runs = sum(o["subdomain_runs"] for g, o, d in results[-1])
-    relax_ms = sum(o["relax_ms"] for g, o, d in results[-1])
+    # per-launch kernel times from the sequential run, where launches do not
+    # overlap (HIP events on each lattice's stream)
+    launches = sum(o["relax_launches"] for g, o, d in results_seq[-1])
+    runs = sum(o["subdomain_runs"] for g, o, d in results_seq[-1])
+    relax_ms = sum(o["relax_ms"] for g, o, d in results_seq[-1])
     repeat_exact = all(np.array_equal(a[2], b[2]) for r in results for a, b in zip(r, results[0]))
     nsub = results[-1][0][1]["n_sub"]
     lnN = math.log(nsub)
@@ -127,7 +141,10 @@ def main():
     roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(PEAK_WAVE_INSTR / 1e9, 1),
                 "unit": "Gwave-instr/s", "frac": round(achieved * 1e9 / PEAK_WAVE_INSTR, 4),
                 "traffic": None, "kernel": "relax_graph_kernel",
-                "avg_launch_us": round(avg_launch_s * 1e6, 2), "launches_per_step": launches}
+                "avg_launch_us": round(avg_launch_s * 1e6, 2), "launches_per_step": launches,
+                "measured_on": "sequential run (launches do not overlap)",
+                # aggregate rate of the concurrent step: algorithmic work / wall time
+                "concurrent_frac": round(WAVE_INSTR_PER_EVENT * processed / dt / PEAK_WAVE_INSTR, 4)}
     traffic_file = os.path.join(ROOT, "profiles", "relax_kernel_medium_traffic.json")
     if os.path.exists(traffic_file):
         import hashlib
@@ -158,8 +175,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": "medium: 1024x1024 periodic Ising, J=1, h=0.1, "
                                f"T in {list(temps)}, Metropolis, random +-1 start, 4096 "
-                               f"subdomains of 16x16, window 0.5, horizon {args.horizon:g}",
-                   "lattices": len(sims), "horizon": args.horizon, "window": 0.5},
+                               f"subdomains of 16x16, window 0.5, horizon {args.horizon:g}; "
+                               "plain form, the lattices on concurrent HIP streams",
+                   "lattices": len(sims), "horizon": args.horizon, "window": 0.5,
+                   "streams": len(sims)},
         "committed_flips_per_step": int(flips),
         "processed_per_committed": round(processed / max(flips, 1), 3),
         "events_per_subdomain_run": round(processed / max(runs, 1), 2),
@@ -168,6 +187,8 @@ def main():
         "ln_N": round(lnN, 3),
         "thm2_ceiling_C2": round(2 * math.e * 13 * lnN + 1, 1),
         "bit_exact_repeat": bool(repeat_exact),
+        "medium_sequential": {"flips_per_s": round(flips / dt_seq, 1), "ms_per_step": round(dt_seq * 1e3, 2),
+                              "bit_exact_vs_concurrent": bool(seq_same)},
         "roofline": roofline,
     }
 
@@ -192,6 +213,7 @@ def main():
     line["medium_batched"] = {"flips_per_s": round(flips_b / dtb, 1), "ms_per_step": round(dtb * 1e3, 2),
                               "bit_exact_vs_plain": bool(same_b and flips_b == flips)}
     line["medium_plain"] = {"flips_per_s": line["value"], "ms_per_step": line["ms_per_step"]}
+    pool.shutdown()
 
     for s in sims:
         s.close()
@@ -230,12 +252,20 @@ def copy_calibration(mb):
     print(json.dumps({"copy_bytes": n, "launches": 3}))
 
 
-def bench_batch(sr, W, stream, torch, n=512, horizon=50.0):
-    """Uneven lattices: one persistent launch vs one plain run per lattice."""
+def bench_batch(sr, W, stream, torch, n=512, horizon=50.0, nstreams=8):
+    """Uneven lattices: one persistent launch vs the plain form (one lattice
+    per launch sequence), the latter both one lattice after the other and
+    with `nstreams` lattices in flight on concurrent streams."""
+    import threading
     import numpy as np
     ps = W.batch(n=n, horizon=horizon)
-    sims = [sr.Sim(p, stream=stream) for p in ps]
+    streams = [torch.cuda.Stream() for _ in range(nstreams)]
+    sims = [sr.Sim(p, stream=streams[i % nstreams]) for i, p in enumerate(ps)]
     log(f"batch: {n} lattices created")
+
+    def digests():
+        return [s.digests()[0].copy() for s in sims]
+
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in sims:
@@ -243,8 +273,27 @@ def bench_batch(sr, W, stream, torch, n=512, horizon=50.0):
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     flips = sum(s.observables()["flips"] for s in sims)
-    dig_plain = [s.digests()[0].copy() for s in sims]
+    dig_plain = digests()
     log(f"batch: plain done in {t_plain:.2f}s")
+
+    for s in sims:
+        s.reset()
+
+    def worker(k):
+        for s in sims[k::nstreams]:
+            s.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    th = [threading.Thread(target=worker, args=(k,)) for k in range(nstreams)]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join()
+    torch.cuda.synchronize()
+    t_conc = time.perf_counter() - t0
+    same_conc = all(np.array_equal(a, b) for a, b in zip(dig_plain, digests()))
+    log(f"batch: plain on {nstreams} streams done in {t_conc:.2f}s")
+
     for s in sims:
         s.reset()
     torch.cuda.synchronize()
@@ -253,17 +302,20 @@ def bench_batch(sr, W, stream, torch, n=512, horizon=50.0):
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     flips_b = sum(s.observables()["flips"] for s in sims)
-    same = all(np.array_equal(a, s.digests()[0]) for a, s in zip(dig_plain, sims))
+    same = all(np.array_equal(a, b) for a, b in zip(dig_plain, digests()))
     log(f"batch: batched done in {t_batch:.2f}s")
     spins = sum(s.observables()["Lx"] * s.observables()["Ly"] for s in sims)
     for s in sims:
         s.close()
-    return {"workload": f"{n} lattices, L uniform on multiples of 16 in [32,512], "
-                        "T~U[1,3.5], h~U[-0.2,0.2], tuned block/window, horizon 50",
+    return {"workload": f"{n} lattices, L uniform on multiples of 16 in [32,512], T~U[1,3.5], "
+                        "h~U[-0.2,0.2], tuned block/window, horizon 50",
             "spins": int(spins), "committed_flips": int(flips),
             "plain_flips_per_s": round(flips / t_plain, 1),
+            f"plain_{nstreams}_streams_flips_per_s": round(flips / t_conc, 1),
             "batched_flips_per_s": round(flips_b / t_batch, 1),
-            "speedup": round(t_plain / t_batch, 3), "bit_exact": bool(same and flips == flips_b)}
+            "speedup": round(t_plain / t_batch, 3),
+            f"speedup_vs_plain_{nstreams}_streams": round(t_conc / t_batch, 3),
+            "bit_exact": bool(same and same_conc and flips == flips_b)}
 
 
 def bench_window_sweep(sr, W, stream, torch, horizon):
