@@ -30,11 +30,13 @@
  * own every host buffer they pass.  All device work of a simulation is
  * ordered on the HIP stream given at creation (NULL = default stream); every
  * call returns only after that work is complete.  Handles are not
- * thread-safe: one host thread per handle at a time.
+ * thread-safe: one host thread per handle at a time; different handles may
+ * be driven from different threads at once (give them different streams so
+ * that their device work overlaps).
  *
  * Errors: functions return SR_OK (0) or a negative SR_E* code; the message of
  * the last failure of a handle is sr_last_error(handle) (creation failures:
- * sr_last_error(NULL)).
+ * sr_last_error(NULL), kept per calling thread).
  */
 #ifndef SR_H
 #define SR_H
@@ -167,7 +169,8 @@ int sr_get_rate_table(sr_sim* s, uint32_t out[10]);
 int sr_save(sr_sim* s, void* host_blob, size_t cap, size_t* n);
 int sr_load(const void* host_blob, size_t n, void* hip_stream, sr_sim** out);
 
-/* Message of the last failure (NULL handle: last creation/load failure). */
+/* Message of the last failure (NULL handle: the calling thread's last
+ * creation / load failure). */
 const char* sr_last_error(const sr_sim* s);
 
 /* ---- batched form: many independent lattices in one persistent launch ----

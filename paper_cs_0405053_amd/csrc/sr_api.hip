@@ -70,7 +70,7 @@ struct sr_sim {
   std::string err;
 };
 
-static std::string g_create_err;
+static thread_local std::string g_create_err;   // per calling thread
 
 #define SR_FAIL(sim, code, ...)                                           \
   do {                                                                    \

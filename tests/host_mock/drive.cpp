@@ -3,6 +3,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "../../include/sr.h"
@@ -144,6 +145,31 @@ static void errors() {
   sr_destroy(s);
 }
 
+// Several threads each drive their own simulations (create, run, observe,
+// fail a creation on purpose, destroy) at the same time.
+static void threads() {
+  std::vector<std::thread> th;
+  for (int t = 0; t < 4; ++t) {
+    th.emplace_back([t]() {
+      for (int i = 0; i < 3; ++i) {
+        sr_params p = params(32 + 16 * ((t + i) % 4), i % 2 ? 0.0 : 0.5, 1.0 + 0.5 * i, 100 * t + i);
+        sr_sim* s = nullptr;
+        CHECK(sr_create(&p, nullptr, &s) == SR_OK);
+        int32_t done = 0;
+        CHECK(sr_run_window(s, -1, nullptr, &done) == SR_OK && done > 0);
+        sr_obs o;
+        CHECK(sr_observables(s, &o) == SR_OK && o.tick == o.horizon_ticks);
+        sr_params bad = p;
+        bad.T = -1.0;
+        sr_sim* b = nullptr;
+        CHECK(sr_create(&bad, nullptr, &b) == SR_EINVAL && std::strstr(sr_last_error(nullptr), "T > 0"));
+        sr_destroy(s);
+      }
+    });
+  }
+  for (auto& x : th) x.join();
+}
+
 int main(int argc, char** argv) {
   if (argc < 2) return 2;
   const char* w = argv[1];
@@ -151,6 +177,7 @@ int main(int argc, char** argv) {
   else if (!std::strcmp(w, "server")) server();
   else if (!std::strcmp(w, "batch")) batch();
   else if (!std::strcmp(w, "errors")) errors();
+  else if (!std::strcmp(w, "threads")) threads();
   else return 2;
   CHECK(sr_mock_live_allocations() == 0);
   std::printf("ok %s\n", w);

@@ -10,11 +10,13 @@
 #include "hip/hip_runtime.h"
 
 #include <cstdio>
+#include <mutex>
 #include <set>
 
 #include "../../paper_cs_0405053_amd/csrc/sr_internal.h"
 
 static std::set<void*> g_dev, g_host, g_ev;
+static std::mutex g_mu;   // the stand-in runtime may be called from several threads
 
 static int env_int(const char* name, int dflt) {
   const char* v = std::getenv(name);
@@ -23,20 +25,24 @@ static int env_int(const char* name, int dflt) {
 
 hipError_t hipMalloc(void** p, size_t n) {
   *p = std::calloc(1, n ? n : 1);
+  std::lock_guard<std::mutex> g(g_mu);
   g_dev.insert(*p);
   return hipSuccess;
 }
 hipError_t hipFree(void* p) {
+  std::lock_guard<std::mutex> g(g_mu);
   if (!g_dev.erase(p)) { std::fprintf(stderr, "hipFree of unknown pointer %p\n", p); std::abort(); }
   std::free(p);
   return hipSuccess;
 }
 hipError_t hipHostMalloc(void** p, size_t n, unsigned) {
   *p = std::calloc(1, n ? n : 1);
+  std::lock_guard<std::mutex> g(g_mu);
   g_host.insert(*p);
   return hipSuccess;
 }
 hipError_t hipHostFree(void* p) {
+  std::lock_guard<std::mutex> g(g_mu);
   if (!g_host.erase(p)) { std::fprintf(stderr, "hipHostFree of unknown pointer %p\n", p); std::abort(); }
   std::free(p);
   return hipSuccess;
@@ -53,10 +59,12 @@ hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
 hipError_t hipDeviceSynchronize() { return hipSuccess; }
 hipError_t hipEventCreate(hipEvent_t* e) {
   *e = (hipEvent_t)std::malloc(8);
+  std::lock_guard<std::mutex> g(g_mu);
   g_ev.insert(*e);
   return hipSuccess;
 }
 hipError_t hipEventDestroy(hipEvent_t e) {
+  std::lock_guard<std::mutex> g(g_mu);
   if (!g_ev.erase(e)) { std::fprintf(stderr, "hipEventDestroy of unknown event\n"); std::abort(); }
   std::free(e);
   return hipSuccess;
@@ -97,7 +105,10 @@ hipError_t hipGraphExecDestroy(hipGraphExec_t g) {
   return hipSuccess;
 }
 
-extern "C" size_t sr_mock_live_allocations() { return g_dev.size() + g_host.size() + g_ev.size(); }
+extern "C" size_t sr_mock_live_allocations() {
+  std::lock_guard<std::mutex> g(g_mu);
+  return g_dev.size() + g_host.size() + g_ev.size();
+}
 
 namespace sr {
 hipError_t launch_relax(const Lattice& L, const Step& st, hipStream_t) {

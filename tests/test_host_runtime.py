@@ -17,20 +17,28 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 MOCK = os.path.join(ROOT, "tests", "host_mock")
 
 
-@pytest.fixture(scope="module")
-def drive(tmp_path_factory):
+def _build(tmp_path_factory, name, sanitize):
     gxx = shutil.which("g++")
     if gxx is None:
         pytest.skip("g++ not available")
-    exe = str(tmp_path_factory.mktemp("host_rt") / "drive")
-    cmd = [gxx, "-std=c++17", "-g", "-O1", "-fsanitize=address,undefined",
-           "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", f"-I{MOCK}",
+    exe = str(tmp_path_factory.mktemp("host_rt") / name)
+    cmd = [gxx, "-std=c++17", "-g", "-O1", *sanitize, "-fno-omit-frame-pointer", "-pthread", f"-I{MOCK}",
            "-x", "c++", os.path.join(ROOT, "paper_cs_0405053_amd", "csrc", "sr_api.hip"),
            "-x", "c++", os.path.join(MOCK, "mock_runtime.cpp"),
            "-x", "c++", os.path.join(MOCK, "drive.cpp"), "-o", exe]
     r = subprocess.run(cmd, capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stderr[-4000:]
     return exe
+
+
+@pytest.fixture(scope="module")
+def drive(tmp_path_factory):
+    return _build(tmp_path_factory, "drive", ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"])
+
+
+@pytest.fixture(scope="module")
+def drive_tsan(tmp_path_factory):
+    return _build(tmp_path_factory, "drive_tsan", ["-fsanitize=thread"])
 
 
 def run(exe, scenario, **env):
@@ -70,3 +78,15 @@ def test_batch_budget_resume_reset(drive, overflow):
 
 def test_checkpoint_and_argument_errors(drive):
     run(drive, "errors")
+
+
+def test_threads_drive_separate_simulations(drive):
+    run(drive, "threads", SR_MOCK_G=3)
+
+
+def test_threads_without_data_races(drive_tsan):
+    # ThreadSanitizer: the only state shared between handles is the
+    # per-thread creation error
+    r = subprocess.run([drive_tsan, "threads"], capture_output=True, text=True, timeout=300,
+                       env=dict(os.environ, SR_MOCK_G="3", TSAN_OPTIONS="halt_on_error=1"))
+    assert r.returncode == 0 and "ok threads" in r.stdout, (r.stdout + r.stderr)[-4000:]
