@@ -53,6 +53,8 @@ def main():
                     help="skip the headline leg (profiling the other legs alone)")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--sequential-only", action="store_true",
+                    help="medium leg without the concurrent run (profiling: launches do not overlap)")
     ap.add_argument("--sweep-horizon", type=float, default=200.0)
     ap.add_argument("--temps", default=None, help="comma list, default all three")
     ap.add_argument("--horizon", type=float, default=100.0,
@@ -119,8 +121,11 @@ def main():
         torch.cuda.synchronize()
         return res, (time.perf_counter() - t0) / max(args.steps, 1)
 
-    results, dt = timed(step, "concurrent")
     results_seq, dt_seq = timed(step_sequential, "sequential")
+    if args.sequential_only:
+        results, dt = results_seq, dt_seq
+    else:
+        results, dt = timed(step, "concurrent")
     seq_same = all(np.array_equal(a[2], b[2]) for a, b in zip(results_seq[-1], results[-1]))
 
     flips = sum(o["flips"] for g, o, d in results[-1])
@@ -176,9 +181,10 @@ def main():
         "config": {"workload": "medium: 1024x1024 periodic Ising, J=1, h=0.1, "
                                f"T in {list(temps)}, Metropolis, random +-1 start, 4096 "
                                f"subdomains of 16x16, window 0.5, horizon {args.horizon:g}; "
-                               "plain form, the lattices on concurrent HIP streams",
+                               + ("plain form, one lattice after the other" if args.sequential_only
+                                  else "plain form, the lattices on concurrent HIP streams"),
                    "lattices": len(sims), "horizon": args.horizon, "window": 0.5,
-                   "streams": len(sims)},
+                   "streams": 1 if args.sequential_only else len(sims)},
         "committed_flips_per_step": int(flips),
         "processed_per_committed": round(processed / max(flips, 1), 3),
         "events_per_subdomain_run": round(processed / max(runs, 1), 2),
