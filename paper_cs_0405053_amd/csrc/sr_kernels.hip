@@ -1091,7 +1091,14 @@ __global__ __launch_bounds__(64) void batch_kernel(BatchArgs B) {
     LatRun* run = &B.run[lat];
     const Step st = step_of(load_run(run, lane));
     relax_subdomain<0, 0>(lats[lat], st, d, tile, &run->fl);
+    // The run ends, and the count below starts, with a lane-0 region; left
+    // alone the compiler merges the two and duplicates the release into both
+    // paths, i.e. two L2 write-backs per task (40% of the batched form's
+    // time).  A convergent no-op on either side keeps one release, executed
+    // by the whole wave.
+    __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __builtin_amdgcn_wave_barrier();
     // count this task down and take the next ticket: both memory-side
     // atomics are in flight together
     int last = 0;
