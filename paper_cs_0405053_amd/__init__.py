@@ -88,6 +88,15 @@ def lib() -> C.CDLL:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_cs_0405053_amd.build`")
+        # One HIP runtime per process: PyTorch ships its own copy, and loaded
+        # before libsr.so it also serves libsr.so; loaded after, it would be a
+        # second runtime in the process, and whichever of the two initialises
+        # last finds no device.  So torch (when installed) comes first, and
+        # torch streams passed to the library belong to the same runtime.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         P = C.c_void_p
         L.sr_create.argtypes = [C.POINTER(Params), P, C.POINTER(P)]

@@ -2,6 +2,8 @@
 parameter validation runs on the host (no device work, no GPU needed)."""
 import re
 import os
+import subprocess
+import sys
 
 import pytest
 
@@ -22,6 +24,18 @@ def test_library_exports_every_declared_symbol():
     for name in declared:
         assert hasattr(lib, name), name
     assert sorted(sr.EXPORTS) == declared
+
+
+def test_one_hip_runtime_per_process():
+    # PyTorch ships its own HIP runtime; the binding loads it before libsr.so
+    # so that both use one runtime (with two, whichever initialises last
+    # finds no device).  A fresh process, loading the library first.
+    code = ("import paper_cs_0405053_amd as sr; sr.lib(); "
+            "print(sorted(set(l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l)))")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    runtimes = eval(r.stdout.strip().splitlines()[-1])
+    assert len(runtimes) == 1, runtimes
 
 
 @pytest.mark.parametrize("bad", [
