@@ -215,7 +215,10 @@ static void free_all(sr_sim* s) {
 // Buffer capacities of a lattice whose windows are at most Wmax ticks, and
 // the device bytes it will own.  Capacities: every rate is at most lambda =
 // 1, so a window holds at most about (sites x window) events: that plus six
-// standard deviations.  Checkpoints every kCkIntPlain events or break points
+// standard deviations, boundary lists in steps of 32 entries (a relaxation
+// wave holds 12 of them in LDS: 3 KB at 32, which lets more waves of the
+// persistent kernel share a CU; an overflow re-runs the window with double
+// capacity and the same result).  Checkpoints every kCkIntPlain events or break points
 // (the persistent kernel uses kCkIntBatch: its tasks wait for their stores at
 // the release, so fewer checkpoints pay there), up to 32 per run, enough for
 // 1.5 x the largest expected count.
@@ -231,7 +234,7 @@ static Plan plan(const sr_params& p, int64_t Wmax) {
   double wt = std::ldexp((double)Wmax, -p.tick_bits);
   double edge = std::max(p.bx, p.by) * wt, blk = (double)p.bx * p.by * wt;
   pl.hcap = (int)std::min((double)kMaxHistCap,
-                          std::max(64.0, std::ceil((edge + 6.0 * std::sqrt(edge) + 16.0) / 64.0) * 64.0));
+                          std::max(32.0, std::ceil((edge + 6.0 * std::sqrt(edge)) / 32.0) * 32.0));
   pl.wcap = (int)std::max(64.0, std::ceil((blk + 6.0 * std::sqrt(blk) + 32.0) / 64.0) * 64.0);
   if (p.hist_cap > 0) pl.hcap = p.hist_cap;
   if (p.wlog_cap > 0) pl.wcap = p.wlog_cap;

@@ -1056,8 +1056,10 @@ constexpr uint32_t kSpinBudget = 20u << 20;
 // wait for the slot of the ticket held, acquire, relax, release, count the
 // task down while taking the next ticket.  A held ticket whose task is not
 // produced yet blocks no one: tasks are produced by deciders, and a wave
-// finishes its current task before it waits.
-__global__ __launch_bounds__(64) void batch_kernel(BatchArgs B) {
+// finishes its current task before it waits.  Registers are capped so that
+// six waves share a SIMD (80 VGPRs and a few spills instead of 105, i.e. four
+// waves): more waves hide more of each task's latency chain.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void batch_kernel(BatchArgs B) {
   extern __shared__ int8_t tile[];
   const int lane = lane_id();
   CLattice* lats = (CLattice*)B.lat;
