@@ -9,9 +9,10 @@
 //
 // Per-wave state lives in registers:
 //   * classes of the owned sites as 4-bit nibbles, lane l owning the S
-//     consecutive local sites [l*S, l*S + S) (row-major), so a wave-wide
-//     prefix over lanes visits sites in ascending local order (Sec. 3 "linear
-//     order" of a class);
+//     local sites l, l + 64, ..., l + 64(S-1) (row-major index) in nibbles
+//     0..S-1, so the members of a class in ascending local order (Sec. 3
+//     "linear order" of a class) are the set bits of the S per-nibble ballots
+//     taken in turn;
 //   * class counts N_k and rates r_k in lanes 0..9, the cumulative weights
 //     C_k = sum_{i<=k} N_i r_i by a 16-lane DPP scan (eqs. biglambda, Wsum);
 //   * the halo spins as four 64-bit masks;
@@ -370,9 +371,8 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
     __syncthreads();
     // classes of owned sites, 4 bits each; unused nibbles hold 0xF
     cls = ~0ull;
-    const int base = lane << sh;
     for (int i = 0; i < S; ++i) {
-      int v = base + i;
+      int v = lane + 64 * i;
       if (v < nblk) {
         int ly = v / bx, lx = v - ly * bx;
         int tp = (ly + 1) * tw + lx + 1;
@@ -509,7 +509,7 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
 
   // move site u (local) by `delta` classes
   auto change = [&](int u, int delta) {
-    int o = u >> sh, sl = (u & (S - 1)) * 4;
+    int o = u & 63, sl = (u >> 6) * 4;
     uint64_t w = rdl64(cls, o);
     int a = (int)((w >> sl) & 15);
     int b = a + delta;
@@ -569,28 +569,28 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
       uint32_t rk = rdl(rate, ks);
       uint32_t idx = udiv_small(target - below, rk);
       // site: the idx-th member of class ks in ascending local order
-      // (eqs. nores, vindex)
-      uint64_t x = cls ^ (0x1111111111111111ull * (uint64_t)ks);
-      uint64_t nz = (x | (x >> 1) | (x >> 2) | (x >> 3)) & 0x1111111111111111ull;
-      uint64_t mm = ~nz & 0x1111111111111111ull;
-      uint32_t cnt = (uint32_t)__popcll(mm);
-      uint32_t incl = wave_incl_scan(cnt);
-      uint32_t excl = incl - cnt;
-      int o = ctz64(ballot(excl <= idx && idx < incl));
-      uint32_t nth = idx - excl;
-      int pos = 0;
-      uint32_t c = (uint32_t)__popcll(mm & 0xFFFFFFFFull);
-      if (nth >= c) { nth -= c; pos = 32; }
-      c = (uint32_t)__popcll((mm >> pos) & 0xFFFFull);
-      if (nth >= c) { nth -= c; pos += 16; }
-      c = (uint32_t)__popcll((mm >> pos) & 0xFFull);
-      if (nth >= c) { nth -= c; pos += 8; }
-      c = (uint32_t)__popcll((mm >> pos) & 0xFull);
-      if (nth >= c) { pos += 4; }
-      const int v = (o << sh) + (int)rdl((uint32_t)(pos >> 2), o);
+      // (eqs. nores, vindex).  Members in nibble i are the set bits of
+      // ballot i; the nibble whose members span idx is found on the scalar
+      // unit, the lane by the count of members in the lanes below it.
+      uint64_t msel = 0;
+      uint32_t seen = 0, before = 0;
+      int isel = 0;
+      for (int i = 0; i < S; ++i) {
+        const uint64_t m = ballot(((cls >> (4 * i)) & 15) == (uint64_t)ks);
+        const uint32_t c = (uint32_t)__popcll(m);
+        const bool here = idx - seen < c;         // seen <= idx < seen + c
+        msel = here ? m : msel;
+        isel = here ? i : isel;
+        before = here ? seen : before;
+        seen += c;
+      }
+      const uint32_t nth = idx - before;
+      const uint32_t nlow = __builtin_amdgcn_mbcnt_hi((uint32_t)(msel >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)msel, 0u));
+      const int v = isel * 64 + ctz64(ballot(nlow == nth) & msel);
       // flip v and re-class it and its in-block neighbours (Sec. 3, O(1))
       const int ly = v / bx, lx = v - ly * bx;
-      const int kv = (int)((rdl64(cls, v >> sh) >> ((v & (S - 1)) * 4)) & 15);
+      const int kv = (int)((rdl64(cls, v & 63) >> ((v >> 6) * 4)) & 15);
       const bool now_up = kv >= 5;
       const int dup = now_up ? 1 : -1;
       if ((bx >= 3 || !wrapx) && (by >= 3 || !wrapy)) {
@@ -602,13 +602,13 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
                             ly > 0 ? v - bx : (wrapy ? v + (by - 1) * bx : -1),
                             ly < by - 1 ? v + bx : (wrapy ? v - (by - 1) * bx : -1)};
         const int dv = now_up ? -5 : 5;
-        uint64_t add = lane == (v >> sh) ? (uint64_t)(int64_t)dv << ((v & (S - 1)) * 4) : 0ull;
+        uint64_t add = lane == (v & 63) ? (uint64_t)(int64_t)dv << ((v >> 6) * 4) : 0ull;
         uint32_t inc = (uint32_t)(lane == kv + dv), dec = (uint32_t)(lane == kv);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int u = nbr[q];
           if (u < 0) continue;
-          const int o = u >> sh, sl = (u & (S - 1)) * 4;
+          const int o = u & 63, sl = (u >> 6) * 4;
           const int a = (int)((rdl64(cls, o) >> sl) & 15);
           add += lane == o ? (uint64_t)(int64_t)dup << sl : 0ull;
           inc += (uint32_t)(lane == a + dup);
@@ -674,27 +674,14 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
   }
   if (nev & 63) log_flush(nev & 63);
 
-  // end-of-window block -> working lattice (the other window parity)
-  // (a lane's S sites are consecutive in one row and S-byte aligned, since
-  // bx, x0 and Lx are multiples of S: one store per lane)
+  // end-of-window block -> working lattice (the other window parity): one
+  // byte per owned site; nibble i of the 64 lanes is 64 consecutive sites
   int8_t* so = spins_at(L, st.wp ^ 1);
-  {
-    const int v = lane << sh;
+  for (int i = 0; i < S; ++i) {
+    const int v = lane + 64 * i;
     if (v < nblk) {
       const int ly = v / bx, lx = v - ly * bx;
-      int8_t* dst = so + (int64_t)(y0 + ly) * L.Lx + x0 + lx;
-      uint64_t b[2] = {0ull, 0ull};
-      for (int i = 0; i < S; ++i) {
-        const uint64_t sb = ((cls >> (4 * i)) & 15) < 5 ? 0x01ull : 0xFFull;
-        b[i >> 3] |= sb << (8 * (i & 7));
-      }
-      if (S == 1) *dst = (int8_t)b[0];
-      else if (S == 2) *reinterpret_cast<uint16_t*>(dst) = (uint16_t)b[0];
-      else if (S == 4) *reinterpret_cast<uint32_t*>(dst) = (uint32_t)b[0];
-      else {
-        reinterpret_cast<uint64_t*>(dst)[0] = b[0];
-        if (S == 16) reinterpret_cast<uint64_t*>(dst)[1] = b[1];
-      }
+      so[(int64_t)(y0 + ly) * L.Lx + x0 + lx] = ((cls >> (4 * i)) & 15) < 5 ? (int8_t)1 : (int8_t)-1;
     }
   }
   // compare step (c): own lists against the previous iteration's, then the
