@@ -48,6 +48,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-persistent-only", action="store_true",
+                    help="batch leg: only the persistent launch, no plain comparison (profiling the "
+                         "persistent kernel: rocprofv3's kernel trace has crashed in the runtime while "
+                         "eight host threads launched graphs)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-medium", action="store_true",
                     help="skip the headline leg (profiling the other legs alone)")
@@ -80,7 +84,7 @@ def main():
     if args.no_medium:
         side = {}
         if not args.no_batch:
-            side["batched_vs_plain"] = bench_batch(sr, W, stream, torch)
+            side["batched_vs_plain"] = bench_batch(sr, W, stream, torch, plain=not args.batch_persistent_only)
         if not args.no_serve:
             side["serving"] = bench_serve(sr, W, stream, n=args.serve_requests)
         if not args.no_sweep:
@@ -226,7 +230,7 @@ def main():
 
     if not args.no_batch:
         try:
-            line["batched_vs_plain"] = bench_batch(sr, W, stream, torch)
+            line["batched_vs_plain"] = bench_batch(sr, W, stream, torch, plain=not args.batch_persistent_only)
         except Exception as e:   # reported, never hidden
             line["batched_vs_plain"] = {"error": repr(e)}
     if not args.no_serve:
@@ -258,10 +262,11 @@ def copy_calibration(mb):
     print(json.dumps({"copy_bytes": n, "launches": 3}))
 
 
-def bench_batch(sr, W, stream, torch, n=512, horizon=50.0, nstreams=8):
+def bench_batch(sr, W, stream, torch, n=512, horizon=50.0, nstreams=8, plain=True):
     """Uneven lattices: one persistent launch vs the plain form (one lattice
     per launch sequence), the latter both one lattice after the other and
-    with `nstreams` lattices in flight on concurrent streams."""
+    with `nstreams` lattices in flight on concurrent streams.  plain=False:
+    the persistent launch alone."""
     import threading
     import numpy as np
     ps = W.batch(n=n, horizon=horizon)
@@ -271,6 +276,19 @@ def bench_batch(sr, W, stream, torch, n=512, horizon=50.0, nstreams=8):
 
     def digests():
         return [s.digests()[0].copy() for s in sims]
+
+    if not plain:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sr.batch_run(sims, stream=stream)
+        torch.cuda.synchronize()
+        t_batch = time.perf_counter() - t0
+        flips_b = sum(s.observables()["flips"] for s in sims)
+        log(f"batch: batched done in {t_batch:.2f}s")
+        for s in sims:
+            s.close()
+        return {"workload": f"{n} lattices (persistent launch only)",
+                "committed_flips": int(flips_b), "batched_flips_per_s": round(flips_b / t_batch, 1)}
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
