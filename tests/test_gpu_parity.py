@@ -77,6 +77,10 @@ CASES = [
     (32, 32, 16, 16, 1.0, 0.05, 2.0, 8.0, 28, "metropolis", "up"),       # sparse, low T
     (48, 32, 16, 16, 2.5, 0.0, 0.75, 3.1, 28, "metropolis", "random"),   # ragged horizon
     (16, 32, 8, 16, 2.2, 0.1, 1.0, 3.0, 28, "metropolis", "random"),     # 2 subdomains / dir
+    (48, 48, 12, 12, 2.5, 0.1, 0.5, 3.0, 28, "metropolis", "random"),    # 144 sites: last nibble partly used
+    (36, 36, 12, 6, 2.0, -0.1, 1.0, 3.0, 28, "glauber", "random"),       # 72 sites, 2 / lane
+    (16, 16, 2, 16, 2.5, 0.0, 1.0, 4.0, 28, "metropolis", "random"),     # 2-wide blocks
+    (4, 4, 4, 4, 2.0, 0.1, 1.0, 6.0, 28, "metropolis", "random"),        # smallest lattice, wraps both ways
 ]
 
 
