@@ -567,22 +567,23 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
       int ks = ctz64(gt);
       uint64_t below = ks ? rdl64(C, ks - 1) : 0ull;
       uint32_t rk = rdl(rate, ks);
-      uint32_t idx = udiv_small(target - below, rk);
+      // uniform: kept on the scalar unit for the comparisons below
+      const uint32_t idx = (uint32_t)__builtin_amdgcn_readfirstlane((int)udiv_small(target - below, rk));
       // site: the idx-th member of class ks in ascending local order
       // (eqs. nores, vindex).  Members in nibble i are the set bits of
-      // ballot i; the nibble whose members span idx is found on the scalar
-      // unit, the lane by the count of members in the lanes below it.
+      // ballot i; the nibble holding member idx is the last one whose count
+      // of members in lower nibbles is <= idx (scalar unit), the lane the
+      // one with exactly that many fewer members in the lanes below it.
       uint64_t msel = 0;
       uint32_t seen = 0, before = 0;
       int isel = 0;
       for (int i = 0; i < S; ++i) {
-        const uint64_t m = ballot(((cls >> (4 * i)) & 15) == (uint64_t)ks);
-        const uint32_t c = (uint32_t)__popcll(m);
-        const bool here = idx - seen < c;         // seen <= idx < seen + c
+        const uint64_t m = ballot(((uint32_t)(cls >> (4 * i)) & 15u) == (uint32_t)ks);
+        const bool here = idx >= seen;
         msel = here ? m : msel;
         isel = here ? i : isel;
         before = here ? seen : before;
-        seen += c;
+        seen += (uint32_t)__popcll(m);
       }
       const uint32_t nth = idx - before;
       const uint32_t nlow = __builtin_amdgcn_mbcnt_hi((uint32_t)(msel >> 32),
