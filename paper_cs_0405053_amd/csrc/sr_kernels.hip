@@ -283,8 +283,10 @@ constexpr int lane_shift(int nblk) {
 
 // BX, BY > 0: the block shape is a compile-time constant (the common shapes
 // get their own instantiation: fewer live scalar registers and constant
-// index arithmetic); 0: read from the lattice.
-template <int BX, int BY, class LT>
+// index arithmetic); 0: read from the lattice.  NW: the lattice has at least
+// two subdomains in each direction, so no block wraps onto itself (the wrap
+// selects on neighbour indices and edge pushes drop out at compile time).
+template <int BX, int BY, bool NW = false, class LT>
 __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int d,
                                                 int8_t* lds, IterFlags* fl) {
   static_assert((BX == 0) == (BY == 0), "both or neither block sides fixed");
@@ -295,7 +297,7 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
   const int cx = d % nbx, cy = d / nbx;
   const int x0 = cx * bx, y0 = cy * by;
   const int nblk = bx * by;
-  const bool wrapx = (nbx == 1), wrapy = (nby == 1);
+  const bool wrapx = !NW && (nbx == 1), wrapy = !NW && (nby == 1);
   const bool first = (st.it == 0);
   const int hcap = L.hcap;
   const int dn = ((cy + nby - 1) % nby) * nbx + cx;
@@ -756,7 +758,7 @@ __device__ __forceinline__ bool inputs_changed(const LT& L, int it, int d) {
   return need;
 }
 
-template <int BX, int BY>
+template <int BX, int BY, bool NW>
 __global__ __launch_bounds__(64) void relax_kernel(Lattice L, Step st) {
   extern __shared__ int8_t tile[];
   const int d = blockIdx.x;
@@ -777,13 +779,13 @@ __global__ __launch_bounds__(64) void relax_kernel(Lattice L, Step st) {
   }
   // the descriptor is read in place from the kernel arguments (constant
   // address space), so rarely used fields need not stay in registers
-  relax_subdomain<BX, BY>(*(CLattice*)__builtin_amdgcn_kernarg_segment_ptr(), st, d, tile, L.flags + st.fi);
+  relax_subdomain<BX, BY, NW>(*(CLattice*)__builtin_amdgcn_kernarg_segment_ptr(), st, d, tile, L.flags + st.fi);
 }
 
 // Graph form of the plain iteration: the window descriptor lives in device
 // memory (written by the host before each replay) and node i of the graph is
 // iteration st.it + i.
-template <int BX, int BY>
+template <int BX, int BY, bool NW>
 __global__ __launch_bounds__(64) void relax_graph_kernel(Lattice L, const Step* stp, int i) {
   extern __shared__ int8_t tile[];
   const int d = blockIdx.x;
@@ -803,7 +805,7 @@ __global__ __launch_bounds__(64) void relax_graph_kernel(Lattice L, const Step* 
     }
     return;
   }
-  relax_subdomain<BX, BY>(*(CLattice*)__builtin_amdgcn_kernarg_segment_ptr(), st, d, tile, L.flags + i);
+  relax_subdomain<BX, BY, NW>(*(CLattice*)__builtin_amdgcn_kernarg_segment_ptr(), st, d, tile, L.flags + i);
 }
 
 // Clears the first n iteration flags (a kernel, so that graphs hold no
@@ -1152,15 +1154,30 @@ __global__ __launch_bounds__(256) void observables_kernel(const int8_t* s, int L
 }
 
 // ------------------------------------------------------------ launchers
+// The instantiation for a lattice's block shape and wrap: 16x16 and 32x32
+// blocks have their own, split by whether a block can wrap onto itself.
+static bool no_wrap(const Lattice& L) { return L.nbx > 1 && L.nby > 1; }
+static const void* relax_kernel_for(const Lattice& L) {
+  const bool nw = no_wrap(L);
+  if (L.bx == 16 && L.by == 16) return nw ? (const void*)relax_kernel<16, 16, true> : (const void*)relax_kernel<16, 16, false>;
+  if (L.bx == 32 && L.by == 32) return nw ? (const void*)relax_kernel<32, 32, true> : (const void*)relax_kernel<32, 32, false>;
+  return (const void*)relax_kernel<0, 0, false>;
+}
+static const void* relax_graph_kernel_for(const Lattice& L) {
+  const bool nw = no_wrap(L);
+  if (L.bx == 16 && L.by == 16)
+    return nw ? (const void*)relax_graph_kernel<16, 16, true> : (const void*)relax_graph_kernel<16, 16, false>;
+  if (L.bx == 32 && L.by == 32)
+    return nw ? (const void*)relax_graph_kernel<32, 32, true> : (const void*)relax_graph_kernel<32, 32, false>;
+  return (const void*)relax_graph_kernel<0, 0, false>;
+}
+
 hipError_t launch_relax(const Lattice& L, const Step& st, hipStream_t stream) {
   size_t lds = relax_lds_bytes(L.bx, L.by, L.hcap);
-  if (L.bx == 16 && L.by == 16)
-    hipLaunchKernelGGL((relax_kernel<16, 16>), dim3(L.nsub), dim3(64), lds, stream, L, st);
-  else if (L.bx == 32 && L.by == 32)
-    hipLaunchKernelGGL((relax_kernel<32, 32>), dim3(L.nsub), dim3(64), lds, stream, L, st);
-  else
-    hipLaunchKernelGGL((relax_kernel<0, 0>), dim3(L.nsub), dim3(64), lds, stream, L, st);
-  return hipGetLastError();
+  Lattice Lc = L;
+  Step sc = st;
+  void* args[] = {&Lc, &sc};
+  return hipLaunchKernel(relax_kernel_for(L), dim3(L.nsub), dim3(64), args, lds, stream);
 }
 
 // A graph of k iterations of one window: clear the flags, then k relaxation
@@ -1190,9 +1207,7 @@ hipError_t build_window_graph(const Lattice& L, const Step* dstep, int k, hipGra
     idx[i] = i;
     void* rargs[] = {&Lc, &sp, &idx[i]};
     hipKernelNodeParams rp = {};
-    rp.func = (L.bx == 16 && L.by == 16)   ? (void*)relax_graph_kernel<16, 16>
-              : (L.bx == 32 && L.by == 32) ? (void*)relax_graph_kernel<32, 32>
-                                           : (void*)relax_graph_kernel<0, 0>;
+    rp.func = const_cast<void*>(relax_graph_kernel_for(L));
     rp.gridDim = dim3(L.nsub);
     rp.blockDim = dim3(64);
     rp.sharedMemBytes = (unsigned)lds;

@@ -91,6 +91,18 @@ def test_gpu_matches_oracle(Lx, Ly, bx, by, T, h, win, hor, tb, rule, init):
     check_against_oracle(p)
 
 
+# one relaxation launch per iteration instead of graph replays (the library
+# reads SR_NO_GRAPHS when a simulation is created): every kernel variant --
+# 16x16 without and with wrap, 32x32, runtime shape
+@pytest.mark.parametrize("case", [CASES[1], CASES[6], CASES[2], CASES[3]])
+def test_plain_launches_without_graphs(monkeypatch, case):
+    monkeypatch.setenv("SR_NO_GRAPHS", "1")
+    Lx, Ly, bx, by, T, h, win, hor, tb, rule, init = case
+    p = W.params(Lx, Ly, bx, by, T=T, h=h, window=win, horizon=hor, seed=1234 + Lx + bx,
+                 tick_bits=tb, rule=rule, init=init)
+    check_against_oracle(p)
+
+
 def test_gpu_user_spins():
     s0 = W.random_spins(32, 32, 77, p_up=0.3)
     p = W.params(32, 32, 16, 16, T=2.0, h=0.1, window=1.0, horizon=3.0, seed=5,
