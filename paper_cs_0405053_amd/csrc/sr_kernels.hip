@@ -565,7 +565,8 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
       last_t = t;
       // class: first k with C_k > target (eqs. Wsum, Wstop)
       uint64_t target = __umul64hi(V, lam);
-      uint64_t gt = ballot(lane < kClasses && C > target);
+      // lanes kClasses..15 hold C = lam and higher rows 0: mask the ballot
+      uint64_t gt = ballot(C > target) & ((1ull << kClasses) - 1);
       int ks = ctz64(gt);
       uint64_t below = ks ? rdl64(C, ks - 1) : 0ull;
       uint32_t rk = rdl(rate, ks);
