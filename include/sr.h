@@ -65,8 +65,7 @@ typedef struct {
   int32_t Lx, Ly;            /* lattice (Sec. 2); 4 <= Lx, Ly; periodic */
   int32_t bx, by;            /* subdomain block (Sec. 5 partition G -> G_i):
                                 Lx % bx == 0, Ly % by == 0, 2 <= bx, by <= 64,
-                                bx*by <= 1024, and bx is a multiple of
-                                max(1, bx*by/64) rounded up to a power of 2.
+                                bx*by <= 1024.
                                 bx = by = 0: chosen by the tuner */
   double J, h, T;            /* coupling J > 0 allowed any sign, field, T > 0 */
   int32_t rule;              /* SR_METROPOLIS or SR_GLAUBER */

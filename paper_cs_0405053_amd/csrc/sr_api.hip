@@ -125,8 +125,6 @@ static const char* check_block(int Lx, int Ly, int bx, int by) {
   if (bx < 2 || by < 2 || bx > 64 || by > 64) return "bx and by must be in [2, 64]";
   if (bx * by > 1024) return "bx*by must be <= 1024";
   if (Lx % bx || Ly % by) return "Lx % bx and Ly % by must be 0";
-  int S = 1 << sites_per_lane_shift(bx * by);
-  if (S > 16 || bx % S) return "bx must be a multiple of the sites per lane";
   return nullptr;
 }
 

@@ -81,6 +81,9 @@ CASES = [
     (36, 36, 12, 6, 2.0, -0.1, 1.0, 3.0, 28, "glauber", "random"),       # 72 sites, 2 / lane
     (16, 16, 2, 16, 2.5, 0.0, 1.0, 4.0, 28, "metropolis", "random"),     # 2-wide blocks
     (4, 4, 4, 4, 2.0, 0.1, 1.0, 6.0, 28, "metropolis", "random"),        # smallest lattice, wraps both ways
+    (48, 48, 24, 24, 2.5, 0.1, 0.5, 2.0, 28, "metropolis", "random"),    # 576 sites: 9 of 16 nibbles used
+    (36, 36, 18, 18, 2.0, 0.0, 1.0, 3.0, 28, "glauber", "random"),       # 324 sites, rows not lane-aligned
+    (60, 30, 20, 6, 2.2, 0.05, 1.0, 3.0, 28, "metropolis", "random"),    # 120 sites, 2 / lane
 ]
 
 
