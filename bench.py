@@ -138,6 +138,7 @@ def main():
     # per-launch kernel times from the sequential run, where launches do not
     # overlap (HIP events on each lattice's stream)
     launches = sum(o["relax_launches"] for g, o, d in results_seq[-1])
+    processed_seq = sum(o["events_processed"] for g, o, d in results_seq[-1])
     runs = sum(o["subdomain_runs"] for g, o, d in results_seq[-1])
     relax_ms = sum(o["relax_ms"] for g, o, d in results_seq[-1])
     repeat_exact = all(np.array_equal(a[2], b[2]) for r in results for a, b in zip(r, results[0]))
@@ -155,7 +156,8 @@ def main():
                 # aggregate rate of the concurrent step: algorithmic work / wall time
                 "concurrent_frac": round(WAVE_INSTR_PER_EVENT * processed / dt / PEAK_WAVE_INSTR, 4)}
     traffic_file = os.path.join(ROOT, "profiles", "relax_kernel_medium_traffic.json")
-    if os.path.exists(traffic_file):
+    # the profiles describe the default workload (horizon 100, three temperatures)
+    if os.path.exists(traffic_file) and args.horizon == 100.0 and args.temps is None:
         import hashlib
         with open(traffic_file) as f:
             tr = json.load(f)
@@ -168,6 +170,21 @@ def main():
             gbps = roofline["traffic"] / avg_launch_s / 1e9
             roofline["hbm_GBps"] = round(gbps, 1)
             roofline["hbm_frac"] = round(gbps / HBM_PEAK_GBPS, 4)
+        # issued instructions (SQ_INSTS_* counters of the same kernel version)
+        # per launch, over this run's launch time: the measured counterpart
+        # of the algorithmic rate above
+        ins_file = os.path.join(ROOT, "profiles", "relax_kernel_medium_instructions.json")
+        if os.path.exists(ins_file):
+            with open(ins_file) as f:
+                ins = json.load(f)
+            if ins.get("kernel_source_sha256") == cur:
+                per = ins["instructions_per_launch"]
+                roofline["issued"] = {
+                    "Ginstr_per_s": round(per / avg_launch_s / 1e9, 1),
+                    "valu_frac": round(ins["valu_per_launch"] / avg_launch_s / PEAK_WAVE_INSTR, 4),
+                    "salu_frac": round(ins["salu_per_launch"] / avg_launch_s / PEAK_WAVE_INSTR, 4),
+                    "instr_per_processed_event": round(per * launches / max(processed_seq, 1), 1),
+                    "source": "profiles/relax_kernel_medium_instructions.json"}
 
     line = {
         "metric": "committed flips/s + relax iters/window, batched vs plain, bit-exact on 1 GPU",
