@@ -263,6 +263,8 @@ def main():
 
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(sr, W, stream, temps)
+        if not args.no_batch and isinstance(line.get("batched_vs_plain"), dict):
+            line["batched_vs_plain"]["cpu_baseline"] = cpu_baseline_batch(sr, W, stream)
 
     print(json.dumps(line), flush=True)
 
@@ -472,6 +474,40 @@ def cpu_baseline(sr, W, stream, temps, horizon=1.0):
     return {"value": round(flips / secs, 1), "unit": "flips/s", "cores": 1, "kind": "oracle",
             "sample": f"medium workload, each of T={list(temps)}, first {horizon} time units "
                       f"({flips} flips, {secs:.1f} s)",
+            "gpu_matches_oracle_on_sample": parity}
+
+
+def cpu_baseline_batch(sr, W, stream, n=512, horizon=0.5, check=3):
+    """The oracle DES on every lattice of the batch workload over its first
+    `horizon` time units, lattices in parallel on host threads (the C oracle
+    runs outside the interpreter lock; each lattice is sequential by
+    construction), with the blocks the tuner gives the GPU path (the
+    trajectory does not depend on the window).  The GPU's state at the same
+    time is checked against it on the first `check` lattices."""
+    import numpy as np
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    ps = []
+    for p in W.batch(n=n, horizon=horizon):
+        bx, by, w = sr.tune(p)
+        ps.append(dict(p, bx=bx, by=by, window=w))
+    threads = max(1, min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))))
+    oracle.lib()                                   # load once, before the threads
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        refs = list(ex.map(lambda p: oracle.des(p, log=False), ps))
+    secs = time.perf_counter() - t0
+    flips = sum(r["n_events"] for r in refs)
+    parity = True
+    for p, ref in zip(ps[:check], refs[:check]):
+        s = sr.Sim(dict(p, bx=0, by=0, window=0.0), stream=stream)
+        s.run()
+        parity &= bool(np.array_equal(s.spins(), ref["spins"]) and
+                       np.array_equal(s.digests()[0], ref["sub_digest"]))
+        s.close()
+    log(f"cpu baseline batch: {flips} flips on {threads} threads in {secs:.1f} s")
+    return {"value": round(flips / secs, 1), "unit": "flips/s", "cores": threads, "kind": "oracle",
+            "sample": f"batch workload, all {n} lattices, first {horizon} time units ({flips} flips, {secs:.1f} s)",
             "gpu_matches_oracle_on_sample": parity}
 
 
