@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 # VALU issue ceiling: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per
 # SIMD every 4 cycles (16 lanes per cycle).
 PEAK_WAVE_INSTR = 256 * 4 * 2.4e9 / 4
+LDS_PEAK_GBPS = 256 * 128 * 2.4e9 / 1e9       # 128 B per clock per CU
 # Algorithmic serial-chain work per processed event (wave instructions):
 # class choice ~25, site choice ~40, re-classing 5 sites ~50, weight scan ~16,
 # next-tick division ~30, record / draw ~25, amortised Philox + fixed-point log
@@ -185,6 +186,13 @@ def main():
                     "salu_frac": round(ins["salu_per_launch"] / avg_launch_s / PEAK_WAVE_INSTR, 4),
                     "instr_per_processed_event": round(per * launches / max(processed_seq, 1), 1),
                     "source": "profiles/relax_kernel_medium_instructions.json"}
+                lds = ins.get("lds")
+                if lds:
+                    lds_bytes = (lds["idx_active_cycles_per_launch"] - lds["bank_conflict_cycles_per_launch"]) * \
+                        lds["bytes_per_active_cycle"]
+                    lds_gbps = lds_bytes / avg_launch_s / 1e9
+                    roofline["lds_GBps"] = round(lds_gbps, 1)
+                    roofline["lds_frac"] = round(lds_gbps / LDS_PEAK_GBPS, 4)
 
     line = {
         "metric": "committed flips/s + relax iters/window, batched vs plain, bit-exact on 1 GPU",
