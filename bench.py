@@ -221,6 +221,8 @@ def main():
         "relax_iters_per_window_max": int(gs.max()),
         "ln_N": round(lnN, 3),
         "thm2_ceiling_C2": round(2 * math.e * 13 * lnN + 1, 1),
+        "boundary_events_f": boundary_f(sims, 20),
+        "thm1_ceiling_C2": round(2 * math.e * lnN + 1, 1),
         "bit_exact_repeat": bool(repeat_exact),
         "medium_sequential": {"flips_per_s": round(flips / dt_seq, 1), "ms_per_step": round(dt_seq * 1e3, 2),
                               "bit_exact_vs_concurrent": bool(seq_same)},
@@ -460,6 +462,33 @@ def bench_serve(sr, W, stream, n=64, rate=200.0, budget_gib=96, wpr=8, n_check=3
             "alone_equals_in_mix": bool(same), "alone_checked": n_check}
 
 
+def boundary_f(sims, windows):
+    """f of the paper's Theorem 1 (own events on boundary sites of one
+    subdomain in one committed window, the largest over subdomains) for the
+    first `windows` windows of each lattice, run one window at a time outside
+    the timed steps."""
+    fs = []
+    for s in sims:
+        s.reset()
+        for _ in range(windows):
+            if len(s.run(1)) == 0:
+                break
+            fs.append(s.observables()["last_f"])
+    return {"mean": round(sum(fs) / max(len(fs), 1), 2), "max": max(fs) if fs else 0,
+            "windows": len(fs)}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(sr, W, stream, temps, horizon=1.0):
     """The oracle DES (single thread by construction: global event order) on
     the first `horizon` time units of every temperature; the GPU's committed
@@ -480,6 +509,7 @@ def cpu_baseline(sr, W, stream, temps, horizon=1.0):
         s.close()
         log(f"cpu baseline T={T}: {ref['n_events']} flips")
     return {"value": round(flips / secs, 1), "unit": "flips/s", "cores": 1, "kind": "oracle",
+            "cpu": cpu_model(),
             "sample": f"medium workload, each of T={list(temps)}, first {horizon} time units "
                       f"({flips} flips, {secs:.1f} s)",
             "gpu_matches_oracle_on_sample": parity}
@@ -515,6 +545,7 @@ def cpu_baseline_batch(sr, W, stream, n=512, horizon=0.5, check=3):
         s.close()
     log(f"cpu baseline batch: {flips} flips on {threads} threads in {secs:.1f} s")
     return {"value": round(flips / secs, 1), "unit": "flips/s", "cores": threads, "kind": "oracle",
+            "cpu": cpu_model(),
             "sample": f"batch workload, all {n} lattices, first {horizon} time units ({flips} flips, {secs:.1f} s)",
             "gpu_matches_oracle_on_sample": parity}
 
