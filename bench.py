@@ -71,8 +71,8 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; "
-                          "--gpus must be 1 (multi-GPU sharding is a design note, not built)"}))
+        print(json.dumps({"error": "the library runs on one GPU only; --gpus must be 1 "
+                          "(sharding across GPUs is designed, not implemented)"}))
         sys.exit(2)
 
     import numpy as np
