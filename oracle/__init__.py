@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the benchmark's
 CPU-baseline leg are the only users.  The GPU library never imports it and it
 never imports the GPU library.  The C source (`sr_oracle.c`) is plain,
-single-threaded and unoptimised; this module is a ctypes driver around it.
+single-threaded and unoptimised; this module is a ctypes wrapper around it.
 
 Entry points:
 
