@@ -75,6 +75,8 @@ def lib():
         L.orc_expq.restype = C.c_uint64
         L.orc_rate_table.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int,
                                      C.POINTER(C.c_uint32)]
+        L.orc_mix64.argtypes = [C.c_uint64]
+        L.orc_mix64.restype = C.c_uint64
         L.orc_event_digest.argtypes = [C.c_int64, C.c_int64]
         L.orc_event_digest.restype = C.c_uint64
         L.orc_select_site.argtypes = [C.POINTER(_Params), C.c_void_p, C.c_int,
@@ -107,6 +109,11 @@ def rate_table(J, h, T, rule="metropolis"):
     if rc != 0:
         raise ValueError("bad rate-table parameters")
     return np.array(list(out), dtype=np.uint32)
+
+
+def mix64(z: int) -> int:
+    """SplitMix64 finaliser (the 64-bit mixer of the event digests)."""
+    return int(lib().orc_mix64(C.c_uint64(z & (2**64 - 1))))
 
 
 def event_digest(tick: int, site: int) -> int:

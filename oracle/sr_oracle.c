@@ -221,13 +221,13 @@ static int64_t next_tick(int64_t anchor, uint64_t E, uint64_t acc, uint64_t lam)
 
 /* Digest of one committed event: order-free sum of a 64-bit mix (SplitMix64
  * finaliser, Steele, Lea & Flood 2014) of (tick, global site). */
-static uint64_t mix64(uint64_t z) {
+uint64_t orc_mix64(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
   return z ^ (z >> 31);
 }
 uint64_t orc_event_digest(int64_t tick, int64_t site) {
-  return mix64(mix64((uint64_t)tick) + (uint64_t)site);
+  return orc_mix64(orc_mix64((uint64_t)tick) + (uint64_t)site);
 }
 
 /* Whole-lattice observables from scratch: M = sum s, bond = sum over right

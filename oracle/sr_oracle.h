@@ -45,6 +45,7 @@ typedef struct {
 void orc_philox4x32_10(const uint32_t key[2], const uint32_t ctr[4], uint32_t out[4]);
 uint64_t orc_expq(uint64_t u, int tick_bits);
 int orc_rate_table(double J, double h, double T, int rule, uint32_t out[10]);
+uint64_t orc_mix64(uint64_t z);
 uint64_t orc_event_digest(int64_t tick, int64_t site);
 int orc_select_site(const orc_params* p, const int8_t* spins, int d, uint64_t V, int64_t* site_out);
 int orc_subdomain_lambda(const orc_params* p, const int8_t* spins, int d, uint64_t* lam_out);

@@ -67,6 +67,41 @@ def test_philox_uniform_bits():
         assert abs(frac - 0.5) < 5 * 0.5 / math.sqrt(words.size)
 
 
+# ----------------------------------------------------------------- digest mixer
+GAMMA = 0x9E3779B97F4A7C15          # SplitMix64's Weyl increment
+
+
+def test_digest_mixer_known_answers():
+    # SplitMix64 (Steele, Lea & Flood, OOPSLA 2014) seeded with 0 returns
+    # mix(k * GAMMA) for k = 1, 2, 3, ...; its published first outputs:
+    assert oracle.mix64(GAMMA) == 0xE220A8397B1DCDAF
+    assert oracle.mix64((2 * GAMMA) & MASK64) == 0x6E789E6AA1B965F4
+    assert oracle.mix64((3 * GAMMA) & MASK64) == 0x06C45D188009454F
+    # one committed event (tick, global site) is folded as mix(mix(tick) + site)
+    rng = np.random.default_rng(4)
+    for t, v in [(0, 0), (1, 2), (2**40 + 3, 1 << 24)] + \
+            [(int(a), int(b)) for a, b in zip(rng.integers(0, 2**46, 50), rng.integers(0, 2**26, 50))]:
+        assert oracle.event_digest(t, v) == oracle.mix64((oracle.mix64(t) + v) & MASK64)
+
+
+def test_digest_mixer_avalanche():
+    # a digest compared in place of a full event list is only as good as the
+    # mixer: flipping any one input bit must flip about half the output bits
+    rng = np.random.default_rng(8)
+    xs = [int(x) for x in rng.integers(0, 2**63, size=300)] + [0, 1, MASK64]
+    flips = np.zeros(64)
+    for x in xs:
+        y = oracle.mix64(x)
+        for b in range(64):
+            flips[b] += bin(y ^ oracle.mix64(x ^ (1 << b))).count("1")
+    flips /= len(xs)
+    # binomial(64, 1/2): mean 32, sd 4 per pair; mean over ~300 pairs
+    assert np.all(np.abs(flips - 32.0) < 1.5), flips.round(2)
+    # distinct event pairs map to distinct digests (no collisions in a sample)
+    ds = {oracle.event_digest(t, v) for t in range(300) for v in range(40)}
+    assert len(ds) == 300 * 40
+
+
 # ----------------------------------------------------------------- -ln U
 mpmath = pytest.importorskip("mpmath")
 mpmath.mp.dps = 50
