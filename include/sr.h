@@ -98,8 +98,10 @@ typedef struct {
   int64_t windows;           /* committed windows so far */
   int64_t iterations;        /* relaxation iterations so far */
   int32_t last_g;            /* iterations of the last committed window */
-  int32_t last_f;            /* max boundary-site events of one subdomain in
-                                the last committed window (Sec. 6 f) */
+  int32_t last_f;            /* f of Sec. 6 for the last committed window:
+                                the most own events on boundary sites of one
+                                subdomain in one iteration, the largest over
+                                the window's iterations */
   int32_t tick_bits;
   int32_t n_sub;             /* number of subdomains */
   int32_t bx, by;            /* block in use */
@@ -163,8 +165,21 @@ int sr_get_carry(sr_sim* s, int64_t* out);
 /* The 10 class rates round(2^28 p_k), class k = 5*[s = -1] + (up neighbours). */
 int sr_get_rate_table(sr_sim* s, uint32_t out[10]);
 
+/* The same table computed from parameters alone, as sr_create computes it
+ * (eqs. hamil, pMin / pglauber in IEEE double on the host; no device work,
+ * so it may be called without a GPU).  Reads J, h, T and rule only.
+ * SR_EINVAL for a null argument, T <= 0, non-finite J, h or T, or an unknown
+ * rule. */
+int sr_rate_table(const sr_params* p, uint32_t out[10]);
+
 /* Checkpoint of the committed state (committed time is a consistent cut,
- * Sec. 4).  sr_save with host_blob = NULL reports the size in *n. */
+ * Sec. 4): committed spins, per-subdomain carry, counters, and for an
+ * SR_INIT_USER simulation its initial spins (so sr_reset works after a
+ * load); a simulation with a tuned step size keeps the step size it had
+ * reached.  sr_save with host_blob = NULL reports the size in *n; the caller
+ * owns the blob.  sr_load creates a new simulation on `hip_stream` that
+ * continues bit for bit where the saved one stood; SR_EINVAL for a blob that
+ * is not a checkpoint of this library version or is truncated. */
 int sr_save(sr_sim* s, void* host_blob, size_t cap, size_t* n);
 int sr_load(const void* host_blob, size_t n, void* hip_stream, sr_sim** out);
 

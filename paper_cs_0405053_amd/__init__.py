@@ -31,7 +31,8 @@ _LOG = {"digest": 0, "full": 1, 0: 0, 1: 1}
 
 # every function the C ABI exports (include/sr.h)
 EXPORTS = ["sr_create", "sr_run_window", "sr_observables", "sr_destroy", "sr_get_spins",
-           "sr_get_log", "sr_get_digests", "sr_get_carry", "sr_get_rate_table", "sr_save",
+           "sr_get_log", "sr_get_digests", "sr_get_carry", "sr_get_rate_table", "sr_rate_table",
+           "sr_save",
            "sr_load", "sr_last_error", "sr_batch_run", "sr_tune", "sr_reset",
            "sr_batch_step", "sr_server_create", "sr_server_submit", "sr_server_pump",
            "sr_server_poll", "sr_server_stats", "sr_server_destroy"]
@@ -109,6 +110,7 @@ def lib() -> C.CDLL:
         L.sr_get_digests.argtypes = [P, P, P]
         L.sr_get_carry.argtypes = [P, P]
         L.sr_get_rate_table.argtypes = [P, P]
+        L.sr_rate_table.argtypes = [C.POINTER(Params), P]
         L.sr_save.argtypes = [P, P, C.c_size_t, C.POINTER(C.c_size_t)]
         L.sr_load.argtypes = [P, C.c_size_t, P, C.POINTER(P)]
         L.sr_last_error.argtypes = [P]
@@ -173,6 +175,17 @@ def tune(p: Dict):
     if rc != SR_OK:
         raise SRError(rc, "tuner rejected the lattice")
     return bx.value, by.value, w.value
+
+
+def rate_table(p: Dict) -> np.ndarray:
+    """The 10 class rates the library computes for these parameters (host
+    only, no device work)."""
+    cp, _ = to_params(p)
+    r = np.zeros(10, dtype=np.uint32)
+    rc = lib().sr_rate_table(C.byref(cp), r.ctypes.data)
+    if rc != SR_OK:
+        raise SRError(rc, "sr_rate_table rejected the parameters")
+    return r
 
 
 class Sim:

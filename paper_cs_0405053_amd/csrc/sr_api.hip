@@ -115,6 +115,13 @@ static int rate_table(double J, double h, double T, int rule, uint32_t out[kClas
   return 0;
 }
 
+extern "C" int sr_rate_table(const sr_params* p, uint32_t out[10]) {
+  if (!p || !out) return SR_EINVAL;
+  if (!(p->T > 0.0) || !std::isfinite(p->T) || !std::isfinite(p->J) || !std::isfinite(p->h))
+    return SR_EINVAL;
+  return rate_table(p->J, p->h, p->T, p->rule, out) == 0 ? SR_OK : SR_EINVAL;
+}
+
 static int sites_per_lane_shift(int nblk) {
   int S = (nblk + 63) / 64, sh = 0;
   while ((1 << sh) < S) sh++;
@@ -276,7 +283,8 @@ static int create_impl(const sr_params* pin, void* stream, sr_sim** out, bool in
   if (p.rule != SR_METROPOLIS && p.rule != SR_GLAUBER) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "unknown rule");
   if (!(p.horizon >= 0.0) || !std::isfinite(p.horizon)) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "horizon must be >= 0");
   if (p.log_mode != SR_LOG_DIGEST && p.log_mode != SR_LOG_FULL) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "unknown log mode");
-  if (p.init == SR_INIT_USER && !p.init_spins) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "SR_INIT_USER needs init_spins");
+  if (p.init == SR_INIT_USER && !p.init_spins && init_state)
+    SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "SR_INIT_USER needs init_spins");
   if (p.init != SR_INIT_RANDOM && p.init != SR_INIT_ALL_UP && p.init != SR_INIT_USER)
     SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "unknown init mode");
   const bool tuned_window = (p.window == 0.0);
@@ -554,7 +562,7 @@ extern "C" int sr_observables(sr_sim* s, sr_obs* o) {
   int64_t fmax = 0;
   for (const Carry& x : c) {
     o->flips += x.flips;
-    fmax = std::max(fmax, x.nbound);
+    fmax = std::max(fmax, x.nbmax);
   }
   o->events_processed = s->events_base;
   o->subdomain_runs = s->runs_base;
@@ -659,24 +667,31 @@ extern "C" int sr_get_rate_table(sr_sim* s, uint32_t out[10]) {
 }
 
 // ------------------------------------------------------------ checkpoint
+// Blob: header, committed spins, committed carry, then (SR_INIT_USER only)
+// the initial spins, so that sr_reset works on a loaded simulation too.  A
+// tuned simulation keeps its tuner state: the step size it had reached and
+// the bounds it adapts within.
 struct SaveHeader {
   char magic[8];
   sr_params p;
   int64_t t_c, windows, iterations, events;
   int32_t last_g, last_f;
-  int32_t nsub, pad;
+  int32_t nsub, tune;
+  int64_t W, Wmin, Wmax;
+  int32_t has_init, pad;
 };
 
 extern "C" int sr_save(sr_sim* s, void* blob, size_t cap, size_t* n) {
   if (!s || !n) return SR_EINVAL;
   size_t nsite = (size_t)s->L.Lx * s->L.Ly;
-  size_t need = sizeof(SaveHeader) + nsite + (size_t)s->L.nsub * sizeof(Carry);
+  const bool has_init = s->init_copy != nullptr;
+  size_t need = sizeof(SaveHeader) + nsite + (size_t)s->L.nsub * sizeof(Carry) + (has_init ? nsite : 0);
   *n = need;
   if (!blob) return SR_OK;
   if (cap < need) SR_FAIL(s, SR_EINVAL, "checkpoint buffer too small (%zu < %zu)", cap, need);
   SaveHeader h;
   std::memset(&h, 0, sizeof(h));
-  std::memcpy(h.magic, "SRCKPT1", 8);
+  std::memcpy(h.magic, "SRCKPT2", 8);
   h.p = s->p;
   h.p.init_spins = nullptr;
   sr_obs o;
@@ -684,32 +699,70 @@ extern "C" int sr_save(sr_sim* s, void* blob, size_t cap, size_t* n) {
   if (rc != SR_OK) return rc;
   h.t_c = s->st.t_c; h.windows = s->windows; h.iterations = s->iterations; h.events = o.events_processed;
   h.last_g = s->last_g; h.last_f = o.last_f; h.nsub = s->L.nsub;
+  h.tune = s->tune ? 1 : 0;
+  h.W = s->W; h.Wmin = s->Wmin; h.Wmax = s->Wmax;
+  h.has_init = has_init ? 1 : 0;
   char* b = (char*)blob;
   std::memcpy(b, &h, sizeof(h));
-  HIP_OR_FAIL(s, hipMemcpyAsync(b + sizeof(h), spins_at(s->L, s->st.wp), nsite, hipMemcpyDeviceToHost, s->stream));
-  HIP_OR_FAIL(s, hipMemcpyAsync(b + sizeof(h) + nsite, carry_at(s->L, s->st.wp), (size_t)s->L.nsub * sizeof(Carry), hipMemcpyDeviceToHost, s->stream));
+  size_t at = sizeof(h);
+  HIP_OR_FAIL(s, hipMemcpyAsync(b + at, spins_at(s->L, s->st.wp), nsite, hipMemcpyDeviceToHost, s->stream));
+  at += nsite;
+  HIP_OR_FAIL(s, hipMemcpyAsync(b + at, carry_at(s->L, s->st.wp), (size_t)s->L.nsub * sizeof(Carry), hipMemcpyDeviceToHost, s->stream));
+  at += (size_t)s->L.nsub * sizeof(Carry);
+  if (has_init) HIP_OR_FAIL(s, hipMemcpyAsync(b + at, s->init_copy, nsite, hipMemcpyDeviceToHost, s->stream));
   HIP_OR_FAIL(s, hipStreamSynchronize(s->stream));
   return SR_OK;
 }
 
 extern "C" int sr_load(const void* blob, size_t n, void* stream, sr_sim** out) {
   if (!blob || !out || n < sizeof(SaveHeader)) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "bad checkpoint");
+  *out = nullptr;
   SaveHeader h;
   std::memcpy(&h, blob, sizeof(h));
-  if (std::memcmp(h.magic, "SRCKPT1", 8) != 0) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "not a checkpoint");
+  if (std::memcmp(h.magic, "SRCKPT2", 8) != 0) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "not a checkpoint");
+  if (h.p.Lx < 4 || h.p.Ly < 4 || h.nsub <= 0) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "bad checkpoint header");
   size_t nsite = (size_t)h.p.Lx * h.p.Ly;
-  if (n < sizeof(h) + nsite + (size_t)h.nsub * sizeof(Carry)) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "truncated checkpoint");
-  int rc = create_impl(&h.p, stream, out, false);
+  size_t need = sizeof(h) + nsite + (size_t)h.nsub * sizeof(Carry) + (h.has_init ? nsite : 0);
+  if (n < need) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "truncated checkpoint");
+  // a tuned simulation is re-created as tuned (the tuner is deterministic,
+  // so the first window, its bounds and the buffer plan come out the same),
+  // then given the step size it had reached
+  sr_params p = h.p;
+  if (h.tune) p.window = 0.0;
+  int rc = create_impl(&p, stream, out, false);
   if (rc != SR_OK) return rc;
   sr_sim* s = *out;
   if (s->L.nsub != h.nsub) { sr_destroy(s); *out = nullptr; SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "checkpoint does not match its parameters"); }
   const char* b = (const char*)blob;
-  HIP_OR_FAIL(s, hipMemcpyAsync(spins_at(s->L, 0), b + sizeof(h), nsite, hipMemcpyHostToDevice, s->stream));
-  HIP_OR_FAIL(s, hipMemcpyAsync(carry_at(s->L, 0), b + sizeof(h) + nsite, (size_t)h.nsub * sizeof(Carry), hipMemcpyHostToDevice, s->stream));
-  HIP_OR_FAIL(s, hipStreamSynchronize(s->stream));
+  size_t at = sizeof(h);
+  auto fail = [&](const char* what) {
+    sr_destroy(s);
+    *out = nullptr;
+    SR_FAIL((sr_sim*)nullptr, SR_EDEVICE, "%s", what);
+  };
+  if (hipMemcpyAsync(spins_at(s->L, 0), b + at, nsite, hipMemcpyHostToDevice, s->stream) != hipSuccess)
+    return fail("checkpoint spins upload failed");
+  at += nsite;
+  if (hipMemcpyAsync(carry_at(s->L, 0), b + at, (size_t)h.nsub * sizeof(Carry), hipMemcpyHostToDevice, s->stream) != hipSuccess)
+    return fail("checkpoint carry upload failed");
+  at += (size_t)h.nsub * sizeof(Carry);
+  if (h.has_init) {
+    if (hipMalloc(&s->init_copy, nsite) != hipSuccess) {
+      sr_destroy(s);
+      *out = nullptr;
+      SR_FAIL((sr_sim*)nullptr, SR_ENOMEM, "cannot allocate initial spins");
+    }
+    if (hipMemcpyAsync(s->init_copy, b + at, nsite, hipMemcpyHostToDevice, s->stream) != hipSuccess)
+      return fail("checkpoint initial spins upload failed");
+  }
+  if (hipStreamSynchronize(s->stream) != hipSuccess) return fail("stream sync failed");
   s->st.t_c = h.t_c; s->st.wp = 0;
   s->windows = h.windows; s->iterations = h.iterations; s->events_base = h.events;
   s->last_g = h.last_g;
+  if (h.tune) {
+    s->tune = true;
+    s->W = h.W; s->Wmin = h.Wmin; s->Wmax = h.Wmax;
+  }
   return SR_OK;
 }
 
@@ -851,8 +904,11 @@ extern "C" int sr_batch_step(sr_sim* const* sims, int32_t n, int32_t max_windows
     s->batch_tasks += r.tasks;
     int one = SR_OK;
     if (r.status == kOverflow) {
-      // grow, then run this step's windows alone from the last committed one
-      one = grow(s, 3u);
+      // grow what overflowed (the decider leaves that iteration's flags in
+      // the lattice record), then run this step's windows alone from the
+      // last committed one
+      uint32_t bits = (r.fl.ovf_hist ? 1u : 0u) | (r.fl.ovf_log ? 2u : 0u);
+      one = grow(s, bits ? bits : 3u);
       if (one == SR_OK) one = sr_run_window(s, max_windows > 0 ? max_windows : -1, nullptr, nullptr);
     } else if (r.status == kNoConv) {
       one = SR_ENOCONV;

@@ -23,9 +23,11 @@ struct alignas(64) Carry {
   uint64_t digest;   // order-free digest of committed events
   int64_t flips;     // committed flips
   int64_t wflips;    // flips of the working window (used by commit)
-  int64_t nbound;    // boundary-site events of the window (the paper's f
-                     // for this subdomain)
-  int64_t pad;
+  int64_t nbound;    // own events on boundary sites in this run's window
+  int64_t nbmax;     // the largest nbound over this window's runs: the
+                     // paper's f (Sec. 6: boundary events of a PE in one
+                     // iteration; a step's f is the largest over its
+                     // iterations) for this subdomain
 };
 
 // Work counters of one subdomain (owned by the wave that runs it: read at the

@@ -445,9 +445,11 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
 #pragma unroll
   for (int e = 0; e < 4; ++e)
     for (int i = lane; i < np[e]; i += 64) lprev[e * hcap + i] = pb[e * hcap + i];
-  // committed digest and flip count of this subdomain, needed at the end
+  // committed digest and flip count of this subdomain, needed at the end;
+  // the largest boundary-event count of its earlier runs in this window
   const uint64_t dig_in = rdl64(cin->digest, 0);
   const int64_t flips_in = (int64_t)rdl64((uint64_t)cin->flips, 0);
+  const int64_t nbmax_in = first ? 0 : (int64_t)rdl64((uint64_t)carry_at(L, st.wp ^ 1)[d].nbmax, 0);
   const unsigned long long ev_in = rdl64(L.stat[d].events, 0), runs_in = rdl64(L.stat[d].runs, 0);
   __syncthreads();
   if (tot > 0) {
@@ -716,6 +718,7 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
     co->flips = flips_in + nev;
     co->wflips = nev;
     co->nbound = nbound;
+    co->nbmax = nbound > nbmax_in ? nbound : nbmax_in;
     L.stat[d].events = ev_in + (unsigned long long)(nev - nev0);
     L.stat[d].runs = runs_in + 1ull;
     L.wcnt[d] = (uint32_t)nev;
@@ -1038,9 +1041,13 @@ __device__ void decide(const BatchArgs& B, int lat, int lane) {
   }
 }
 
-// Empty polls of one queue slot before the kernel gives up (about ten
-// seconds; a task takes microseconds to milliseconds).
+// Empty polls of one queue slot, with no task finished anywhere in the grid
+// meanwhile, before the kernel gives up (about ten seconds; a task takes
+// microseconds to milliseconds).  Progress is the sum of the shards' ticket
+// counters (every finished task takes a ticket), read every kProgressEvery
+// polls; a wave whose shard has no work while others do keeps waiting.
 constexpr uint32_t kSpinBudget = 20u << 20;
+constexpr uint32_t kProgressEvery = 4096;
 
 // Wave w serves shard w % kShards (consecutive workgroups go to different
 // XCDs, so each shard's counters are hit mostly from one XCD).  Per task:
@@ -1064,13 +1071,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void ba
     const uint32_t want = (uint32_t)(t + 1);
     unsigned long long v;
     uint32_t spins = 0;
+    unsigned long long seen = 0;
     for (;;) {
       v = __hip_atomic_load(&qg[t & B.qmask], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if ((uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32)) == want) break;
       if (__hip_atomic_load(&B.ctr->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= B.nlat) return;
       if (__hip_atomic_load(&B.ctr->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-      if (++spins > kSpinBudget) {
-        // far longer than any task takes: give up rather than hang
+      if (++spins % kProgressEvery == 0) {
+        unsigned long long prog = 0;
+#pragma unroll
+        for (int k = 0; k < kShards; ++k)
+          prog += __hip_atomic_load(&B.ctr->sh[k].head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        prog = ((uint64_t)rdl((uint32_t)(prog >> 32), 0) << 32) | rdl((uint32_t)prog, 0);
+        if (prog != seen) { seen = prog; spins = 0; }
+      }
+      if (spins > kSpinBudget) {
+        // no task finished anywhere for far longer than any task takes: give
+        // up rather than hang
         if (lane == 0) __hip_atomic_store(&B.ctr->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return;
       }

@@ -100,8 +100,12 @@ static void server() {
 // path (buffers grown, the window re-run from its committed state).
 static void batch() {
   std::vector<sr_sim*> sims;
+  const char* ovf = std::getenv("SR_MOCK_OVERFLOW");
   for (int i = 0; i < 5; ++i) {
     sr_params p = params(32 + 16 * i, i % 2 ? 0.0 : 0.5, 2.0 + i, 100 + i);
+    // lattice 0 already at the largest list capacity: an overflow of its
+    // window log alone must grow the log, not fail on the lists
+    if (i == 0 && ovf && std::atoi(ovf) == 2) p.hist_cap = 1024;
     sr_sim* s = nullptr;
     CHECK(sr_create(&p, nullptr, &s) == SR_OK);
     sims.push_back(s);
@@ -135,6 +139,52 @@ static void errors() {
   CHECK(sr_observables(s, &a) == SR_OK && sr_observables(t, &b) == SR_OK);
   CHECK(a.tick == b.tick && a.windows == b.windows && a.M == b.M);
   sr_destroy(t);
+  // a user start survives a checkpoint: the loaded copy can be reset
+  {
+    sr_params u = params(32, 0.5, 2.0, 9);
+    std::vector<int8_t> sp(32 * 32);
+    for (size_t i = 0; i < sp.size(); ++i) sp[i] = (i * 7 % 3) ? 1 : -1;
+    u.init = SR_INIT_USER;
+    u.init_spins = sp.data();
+    sr_sim* a = nullptr;
+    CHECK(sr_create(&u, nullptr, &a) == SR_OK);
+    CHECK(sr_run_window(a, 2, nullptr, nullptr) == SR_OK);
+    size_t m = 0;
+    CHECK(sr_save(a, nullptr, 0, &m) == SR_OK);
+    std::vector<char> ub(m);
+    CHECK(sr_save(a, ub.data(), m, &m) == SR_OK);
+    sr_sim* c = nullptr;
+    CHECK(sr_load(ub.data(), ub.size(), nullptr, &c) == SR_OK);
+    CHECK(sr_reset(c) == SR_OK && sr_reset(a) == SR_OK);
+    sr_obs oa, oc;
+    CHECK(sr_observables(a, &oa) == SR_OK && sr_observables(c, &oc) == SR_OK);
+    CHECK(oa.tick == 0 && oc.tick == 0 && oa.M == oc.M);
+    sr_destroy(a);
+    sr_destroy(c);
+  }
+  // a tuned step size survives a checkpoint
+  {
+    sr_params q = params(64, 0.0, 3.0, 11);
+    sr_sim* a = nullptr;
+    CHECK(sr_create(&q, nullptr, &a) == SR_OK);
+    sr_obs o0, oa, oc;
+    CHECK(sr_observables(a, &o0) == SR_OK);
+    CHECK(sr_run_window(a, 3, nullptr, nullptr) == SR_OK);
+    CHECK(sr_observables(a, &oa) == SR_OK && oa.window_ticks != o0.window_ticks);
+    size_t m = 0;
+    CHECK(sr_save(a, nullptr, 0, &m) == SR_OK);
+    std::vector<char> qb(m);
+    CHECK(sr_save(a, qb.data(), m, &m) == SR_OK);
+    sr_sim* c = nullptr;
+    CHECK(sr_load(qb.data(), qb.size(), nullptr, &c) == SR_OK);
+    CHECK(sr_observables(c, &oc) == SR_OK);
+    CHECK(oc.window_ticks == oa.window_ticks && oc.tick == oa.tick && oc.windows == oa.windows);
+    int32_t da = 0, dc = 0;
+    CHECK(sr_run_window(a, -1, nullptr, &da) == SR_OK && sr_run_window(c, -1, nullptr, &dc) == SR_OK);
+    CHECK(da == dc);
+    sr_destroy(a);
+    sr_destroy(c);
+  }
   sr_params bad = p;
   bad.bx = 3; bad.by = 3;
   CHECK(sr_create(&bad, nullptr, &t) == SR_EINVAL);

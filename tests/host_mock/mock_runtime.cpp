@@ -5,8 +5,9 @@
 //   relaxation  -- a window converges after SR_MOCK_G iterations (default 1);
 //   batch       -- every lattice commits windows of its current length, with
 //                  the same step-size rule and window budget as the device
-//                  decider; SR_MOCK_OVERFLOW=1 makes lattice 0 report a
-//                  buffer overflow so that the plain fallback runs.
+//                  decider; SR_MOCK_OVERFLOW=1 makes lattice 0 report an
+//                  overflow of both buffers (2: of its window log only) so
+//                  that the plain fallback runs.
 #include "hip/hip_runtime.h"
 
 #include <cstdio>
@@ -136,7 +137,15 @@ hipError_t launch_batch(const BatchArgs& B, int, size_t, hipStream_t) {
   const int G = env_int("SR_MOCK_G", 1);
   for (uint32_t k = 0; k < B.nlat; ++k) {
     LatRun& r = B.run[k];
-    if (k == 0 && env_int("SR_MOCK_OVERFLOW", 0)) { r.status = kOverflow; continue; }
+    const int ovf = env_int("SR_MOCK_OVERFLOW", 0);
+    if (k == 0 && ovf) {
+      // 1: both buffers overflowed; 2: only the window log did
+      r.status = kOverflow;
+      r.fl.ovf_hist = ovf == 1;
+      r.fl.ovf_log = 1;
+      B.ctr->done++;
+      continue;
+    }
     int budget = r.win_budget;
     r.status = kRunning;
     while (r.status == kRunning) {

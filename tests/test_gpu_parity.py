@@ -176,3 +176,119 @@ def test_no_convergence_leaves_state_committed():
     assert e.value.code == sr.SR_ENOCONV
     assert np.array_equal(s.spins(), before)
     assert s.observables()["tick"] == 0
+
+
+# ---- edge cases of the method
+def test_zero_total_rate_subdomains():
+    """T = 0.1: every uphill rate rounds to 0, so subdomains whose sites sit
+    in zero-rate classes have Lambda = 0 (no pending event until a neighbour
+    flip changes their halo).  A half-up / half-down start puts whole blocks
+    there from time 0; the random start freezes into domains."""
+    rates = oracle.rate_table(1.0, 0.05, 0.1)
+    assert (rates == 0).sum() >= 4
+    s0 = np.ones((64, 64), dtype=np.int8)
+    s0[:, 32:] = -1
+    s0[10:20, 5:9] = -1                       # a few unstable sites to start
+    for init, spins in (("user", s0), ("random", None)):
+        p = W.params(64, 64, 16, 16, T=0.1, h=0.05, window=0.5, horizon=6.0, seed=77,
+                     init=init, init_spins=spins)
+        check_against_oracle(p)
+
+
+@pytest.mark.parametrize("J,h,T,rule", [(-1.0, 0.0, 1.5, "metropolis"), (-1.0, 0.3, 2.5, "glauber"),
+                                        (-0.5, -0.1, 0.8, "metropolis")])
+def test_antiferromagnetic_coupling(J, h, T, rule):
+    p = W.params(48, 32, 16, 16, T=T, h=h, J=J, window=0.75, horizon=3.0, seed=501, rule=rule)
+    check_against_oracle(p)
+
+
+def _random_case(rng):
+    # block sides 2..32 with bx*by <= 1024, 1..4 blocks per direction (lattice
+    # sides >= 4), any tick resolution the library accepts, either rule, any
+    # sign of J and h, windows from a few ticks to longer than the horizon
+    while True:
+        bx, by = int(rng.integers(2, 33)), int(rng.integers(2, 33))
+        nbx, nby = int(rng.integers(1, 5)), int(rng.integers(1, 5))
+        Lx, Ly = bx * nbx, by * nby
+        if bx * by <= 1024 and Lx >= 4 and Ly >= 4 and Lx * Ly <= 96 * 96:
+            break
+    tb = int(rng.choice([4, 6, 10, 16, 28]))
+    horizon = float(rng.uniform(0.5, 3.0))
+    window = float(rng.choice([rng.uniform(0.05, 0.5), rng.uniform(0.5, 2.0), 4.0]))
+    window = max(window, 2.0 ** -tb)
+    return W.params(Lx, Ly, bx, by, T=float(rng.uniform(0.7, 4.0)), h=float(rng.uniform(-0.5, 0.5)),
+                    J=float(rng.choice([1.0, 1.0, 0.5, -1.0])), window=window, horizon=horizon,
+                    seed=int(rng.integers(0, 2**63)), tick_bits=tb,
+                    rule=["metropolis", "glauber"][int(rng.integers(0, 2))],
+                    init=["random", "up"][int(rng.integers(0, 4)) == 0])
+
+
+def test_randomised_small_lattices():
+    """A seeded sweep over shapes, blocks, tick resolutions, windows and
+    parameters; stops at the first case that differs from the oracle."""
+    rng = np.random.default_rng(20260)
+    for i in range(40):
+        p = _random_case(rng)
+        say("random case", i)
+        check_against_oracle(p)
+
+
+@pytest.mark.parametrize("case", [CASES[1], CASES[3], CASES[8], CASES[10]])
+def test_boundary_events_f_per_window(case):
+    """f of Sec. 6 (most own events on boundary sites of one subdomain in one
+    iteration, the largest over the window's iterations) for every window,
+    against the literal CPU relaxation."""
+    Lx, Ly, bx, by, T, h, win, hor, tb, rule, init = case
+    p = W.params(Lx, Ly, bx, by, T=T, h=h, window=win, horizon=hor, seed=1234 + Lx + bx,
+                 tick_bits=tb, rule=rule, init=init)
+    srr = oracle.sr(p, log=False)
+    sr = _sr()
+    sim = sr.Sim(dict(p, log_mode="digest"))
+    fs, gs = [], []
+    while True:
+        g = sim.run(1)
+        if len(g) == 0:
+            break
+        gs.append(int(g[0]))
+        fs.append(sim.observables()["last_f"])
+    sim.close()
+    assert gs == srr["g"].tolist()
+    assert fs == srr["f"].tolist(), (fs, srr["f"].tolist())
+
+
+def test_created_rate_tables_equal_oracle():
+    sr = _sr()
+    ps = [W.small(), *[W.medium(T=T, horizon=1.0) for T in W.MEDIUM_TEMPS]]
+    ps += [W.params(32, 32, 16, 16, T=T, h=h, J=J, rule=r, window=1.0, horizon=1.0)
+           for (J, h, T, r) in [(1.0, 0.1, 0.1, "metropolis"), (-1.0, 0.2, 1.3, "glauber"),
+                                (0.0, 0.0, 1.0, "metropolis")]]
+    for p in ps:
+        s = sr.Sim(dict(p, log_mode="digest"))
+        assert np.array_equal(s.rate_table(), oracle.rate_table(p["J"], p["h"], p["T"], p["rule"]))
+        s.close()
+
+
+def test_checkpoint_user_start_and_tuned_window():
+    """A user start and a tuned step size survive sr_save / sr_load: the
+    loaded simulation continues bit for bit, and reset works on it."""
+    sr = _sr()
+    s0 = W.random_spins(48, 48, 5, p_up=0.6)
+    for p in (W.params(48, 48, 16, 16, T=2.2, h=0.1, window=0.5, horizon=5.0, seed=8, init="user",
+                       init_spins=s0, log_mode="digest"),
+              W.params(64, 64, 0, 0, T=2.6, h=-0.1, window=0.0, horizon=6.0, seed=9, log_mode="digest")):
+        a = sr.Sim(p)
+        a.run()
+        b = sr.Sim(p)
+        b.run(4)
+        c = sr.Sim.load(b.save())
+        assert c.observables()["window_ticks"] == b.observables()["window_ticks"]
+        b.close()
+        c.run()
+        assert np.array_equal(a.spins(), c.spins())
+        assert np.array_equal(a.digests()[0], c.digests()[0])
+        assert np.array_equal(a.carry(), c.carry())
+        c.reset()
+        c.run()
+        assert np.array_equal(a.spins(), c.spins())
+        a.close()
+        c.close()

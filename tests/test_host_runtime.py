@@ -76,6 +76,12 @@ def test_batch_budget_resume_reset(drive, overflow):
     run(drive, "batch", SR_MOCK_G=4, SR_MOCK_OVERFLOW=overflow)
 
 
+def test_batch_log_overflow_at_list_capacity_limit(drive):
+    # only the window log overflowed, on a lattice whose lists are already at
+    # their largest capacity: the fallback grows the log and completes
+    run(drive, "batch", SR_MOCK_G=4, SR_MOCK_OVERFLOW=2)
+
+
 def test_checkpoint_and_argument_errors(drive):
     run(drive, "errors")
 
