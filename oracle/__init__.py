@@ -32,6 +32,7 @@ _lib = None
 METROPOLIS, GLAUBER = 0, 1
 INIT = {"random": 0, "up": 1, "user": 2}
 RULE = {"metropolis": 0, "glauber": 1, 0: 0, 1: 1}
+STEP = {"continue": 0, "wipe": 1, 0: 0, 1: 1}
 
 
 def build() -> str:
@@ -48,7 +49,8 @@ class _Params(C.Structure):
                 ("T", C.c_double), ("rule", C.c_int32), ("tick_bits", C.c_int32),
                 ("init", C.c_int32), ("window_ticks", C.c_int64),
                 ("horizon_ticks", C.c_int64), ("burn_ticks", C.c_int64),
-                ("seed", C.c_uint64), ("init_spins", C.c_void_p)]
+                ("seed", C.c_uint64), ("init_spins", C.c_void_p),
+                ("step_rule", C.c_int32)]
 
 
 class _Result(C.Structure):
@@ -140,6 +142,7 @@ def _cparams(p, burn=0.0, window=None):
     cp.horizon_ticks = to_ticks(p["horizon"], tb)
     cp.burn_ticks = to_ticks(burn, tb)
     cp.seed = p["seed"] & (2**64 - 1)
+    cp.step_rule = STEP[p.get("step", "continue")]
     keep = None
     if cp.init == 2:
         keep = np.ascontiguousarray(p["init_spins"], dtype=np.int8).reshape(-1)

@@ -48,7 +48,13 @@
  *    site from the state before that tick;
  *  - windows are half open [t_c, t_c + W); the window edge is not a break
  *    point: the pending draw and its integrated hazard carry over (Sec. 5,
- *    "Subsequent steps"), so the trajectory does not depend on W.
+ *    "Subsequent steps"), so the trajectory does not depend on W;
+ *  - or, with ORC_STEP_WIPE (Sec. 5, "An alternate approach to subsequent
+ *    steps"), every step start t_c > 0 empties every subdomain's pending
+ *    event: the pending pair is discarded, the next pair of the subdomain's
+ *    list (one later than any used so far) is drawn, and its hazard starts
+ *    at t_c.  Poisson memorylessness keeps this unbiased; the trajectory
+ *    then depends on W.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -158,6 +164,7 @@ static int lat_init(lat_t* L, const orc_params* p) {
   if (p->Lx % p->bx || p->Ly % p->by) return -1;
   if (p->tick_bits < 1 || p->tick_bits > 28) return -1;
   if (p->window_ticks < 1 || p->horizon_ticks < 0) return -1;
+  if (p->step_rule != ORC_STEP_CONTINUE && p->step_rule != ORC_STEP_WIPE) return -1;
   if ((int64_t)p->bx * p->by > 4096) return -1;
   L->Lx = p->Lx; L->Ly = p->Ly; L->bx = p->bx; L->by = p->by;
   L->nbx = p->Lx / p->bx; L->nby = p->Ly / p->by;
@@ -389,9 +396,25 @@ int orc_des_run(const orc_params* p, orc_result* r) {
     if (r->sub_digest) r->sub_digest[d] = 0;
   }
 
+  int64_t next_wipe = p->window_ticks;   /* next step start (wipe rule) */
   for (;;) {
     int64_t t = T.key[1];
     int64_t stop = p->horizon_ticks;
+    /* wipe rule: at each step start t_c in (0, horizon) reached before the
+     * next event, every subdomain forgets its pending event and draws its
+     * next pair afresh, with the hazard counted from t_c */
+    while (p->step_rule == ORC_STEP_WIPE && next_wipe < stop && next_wipe <= t) {
+      for (int d = 0; d < L.nsub; ++d) {
+        sub[d].j += 1;
+        sub[d].anchor = next_wipe;
+        sub[d].acc = 0;
+        draw(&L, d, sub[d].j, &sub[d].E, &sub[d].V);
+        sub[d].next = next_tick(next_wipe, sub[d].E, 0, sub[d].lam);
+        tree_set(&T, d, sub[d].next);
+      }
+      next_wipe += p->window_ticks;
+      t = T.key[1];
+    }
     int64_t t_eff = t < stop ? t : stop;
     /* committed-time snapshots: state after all flips with tick < k W */
     while (snap <= nwin) {
@@ -727,6 +750,15 @@ int orc_sr_run(const orc_params* p, orc_result* r, int32_t* g_out, int32_t* f_ou
     int64_t t_end = t_c + p->window_ticks;
     if (t_end > p->horizon_ticks) t_end = p->horizon_ticks;
     int it, converged = 0, fmax = 0;
+    if (p->step_rule == ORC_STEP_WIPE && t_c > 0) {
+      /* wipe the slate: the pending pair of every subdomain is dropped and
+       * the next one starts its hazard at t_c */
+      for (int d = 0; d < nsub; ++d) {
+        carry[d].j += 1;
+        carry[d].anchor = t_c;
+        carry[d].acc = 0;
+      }
+    }
     for (it = 0; it < max_iters; ++it) {
       int cur = it & 1, prev = cur ^ 1;
       for (int d = 0; d < nsub; ++d) {

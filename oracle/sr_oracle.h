@@ -10,6 +10,10 @@
 
 enum { ORC_METROPOLIS = 0, ORC_GLAUBER = 1 };
 enum { ORC_INIT_RANDOM = 0, ORC_INIT_ALL_UP = 1, ORC_INIT_USER = 2 };
+/* Sec. 5: subsequent steps continue the pending random pair and its
+ * integrated hazard ("Subsequent steps"), or wipe the slate at every step
+ * start ("An alternate approach to subsequent steps"). */
+enum { ORC_STEP_CONTINUE = 0, ORC_STEP_WIPE = 1 };
 
 typedef struct {
   int32_t Lx, Ly;          /* periodic lattice, Lx, Ly >= 2 */
@@ -23,6 +27,7 @@ typedef struct {
   int64_t burn_ticks;      /* time integrals start here */
   uint64_t seed;
   const int8_t* init_spins;/* Ly*Lx, for ORC_INIT_USER */
+  int32_t step_rule;       /* ORC_STEP_CONTINUE or ORC_STEP_WIPE (Sec. 5) */
 } orc_params;
 
 typedef struct {

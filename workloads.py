@@ -37,13 +37,15 @@ SEED_BASE = 0x5EED0000
 
 def params(Lx, Ly, bx, by, T, h=0.0, J=1.0, window=1.0, horizon=1.0, seed=1,
            init="random", rule="metropolis", tick_bits=28, init_spins=None,
-           max_iters=0, log_mode="full") -> Dict:
-    """One lattice run description (plain dict, shared vocabulary)."""
+           max_iters=0, log_mode="full", step="continue") -> Dict:
+    """One lattice run description (plain dict, shared vocabulary).  `step`:
+    "continue" (pending random pairs carry over between steps) or "wipe"
+    (every step starts afresh)."""
     return dict(Lx=int(Lx), Ly=int(Ly), bx=int(bx), by=int(by), J=float(J),
                 h=float(h), T=float(T), rule=rule, window=float(window),
                 horizon=float(horizon), seed=int(seed), init=init,
                 tick_bits=int(tick_bits), init_spins=init_spins,
-                max_iters=int(max_iters), log_mode=log_mode)
+                max_iters=int(max_iters), log_mode=log_mode, step=step)
 
 
 def small() -> Dict:
@@ -104,6 +106,21 @@ def serve_stream(n: int = 2000, rate: float = 200.0, seed: int = SEED_BASE + 5,
         p["req_id"] = i
         out.append(p)
     return out
+
+
+def tuned_block(Lx: int, Ly: int, T: float):
+    """The subdomain block the library's tuner assigns to a lattice (a fixed
+    table, so that the block, which keys the random streams, depends on the
+    request alone): 16x16, or 32x32 for lattices of side >= 2048 at T <= 1.25
+    (sparse flips), halved until it divides both sides.  Stated here so that
+    stored oracle results of tuned workloads are computed from inputs alone;
+    the GPU tests check that the tuner agrees."""
+    b = 16
+    if min(Lx, Ly) >= 2048 and T <= 1.25:
+        b = 32
+    while b > 2 and (Lx % b or Ly % b):
+        b >>= 1
+    return b, b
 
 
 def random_spins(Lx: int, Ly: int, seed: int, p_up: float = 0.5) -> np.ndarray:
