@@ -60,6 +60,15 @@ enum {
 enum { SR_METROPOLIS = 0, SR_GLAUBER = 1 };                 /* eq. pMin / eq. pglauber */
 enum { SR_INIT_RANDOM = 0, SR_INIT_ALL_UP = 1, SR_INIT_USER = 2 };
 enum { SR_LOG_DIGEST = 0, SR_LOG_FULL = 1 };
+/* How a step (window) starts after the first (Sec. 5).  SR_STEP_CONTINUE:
+ * each subdomain's pending random pair, the tick of its last event or break
+ * point and the hazard integrated since carry over, so the trajectory does
+ * not depend on the window.  SR_STEP_WIPE ("wipe the slate"): at every step
+ * start t_c > 0 each subdomain drops its pending event and takes the next
+ * pair of its list (one later than any used so far), its hazard counted from
+ * t_c; unbiased by Poisson memorylessness, but the trajectory depends on the
+ * window, which must then be fixed (window > 0). */
+enum { SR_STEP_CONTINUE = 0, SR_STEP_WIPE = 1 };
 
 typedef struct {
   int32_t Lx, Ly;            /* lattice (Sec. 2); 4 <= Lx, Ly; periodic */
@@ -87,6 +96,9 @@ typedef struct {
                                 SR_EINVAL above) */
   int32_t wlog_cap;          /* initial events per subdomain and window
                                 (0 = sized from the window; grown likewise) */
+  int32_t step_rule;         /* SR_STEP_CONTINUE (0) or SR_STEP_WIPE: Sec. 5,
+                                "Subsequent steps" vs "An alternate approach
+                                to subsequent steps" (see below) */
 } sr_params;
 
 typedef struct {

@@ -28,6 +28,7 @@ SR_OK, SR_EINVAL, SR_ENOMEM, SR_EOVERFLOW, SR_ENOCONV, SR_EDEVICE, SR_EDONE = 0,
 _RULE = {"metropolis": 0, "glauber": 1, 0: 0, 1: 1}
 _INIT = {"random": 0, "up": 1, "user": 2, 0: 0, 1: 1, 2: 2}
 _LOG = {"digest": 0, "full": 1, 0: 0, 1: 1}
+_STEP = {"continue": 0, "wipe": 1, 0: 0, 1: 1}
 
 # every function the C ABI exports (include/sr.h)
 EXPORTS = ["sr_create", "sr_run_window", "sr_observables", "sr_destroy", "sr_get_spins",
@@ -50,7 +51,7 @@ class Params(C.Structure):
                 ("window", C.c_double), ("horizon", C.c_double), ("seed", C.c_uint64),
                 ("init", C.c_int32), ("init_spins", C.c_void_p), ("log_mode", C.c_int32),
                 ("max_iters", C.c_int32), ("tick_bits", C.c_int32), ("hist_cap", C.c_int32),
-                ("wlog_cap", C.c_int32)]
+                ("wlog_cap", C.c_int32), ("step_rule", C.c_int32)]
 
 
 class Obs(C.Structure):
@@ -159,6 +160,7 @@ def to_params(p: Dict) -> (Params, Optional[np.ndarray]):
     cp.tick_bits = int(p.get("tick_bits", 0))
     cp.hist_cap = int(p.get("hist_cap", 0))
     cp.wlog_cap = int(p.get("wlog_cap", 0))
+    cp.step_rule = _STEP[p.get("step", "continue")]
     return cp, keep
 
 

@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <chrono>
 #include <deque>
+#include <mutex>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -31,6 +32,7 @@ hipError_t launch_fill(int8_t* s, int64_t n, int8_t v, hipStream_t stream);
 hipError_t launch_observables(const int8_t* s, int Lx, int Ly, unsigned long long* out,
                               hipStream_t stream);
 hipError_t launch_batch(const BatchArgs& B, int waves, size_t lds, hipStream_t stream);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t stream);
 hipError_t build_window_graph(const Lattice& L, const Step* dstep, int k, hipGraphExec_t* out);
 int batch_waves_per_cu(size_t lds);
 size_t relax_lds(const Lattice& L);
@@ -132,6 +134,14 @@ static const char* check_block(int Lx, int Ly, int bx, int by) {
   if (bx < 2 || by < 2 || bx > 64 || by > 64) return "bx and by must be in [2, 64]";
   if (bx * by > 1024) return "bx*by must be <= 1024";
   if (Lx % bx || Ly % by) return "Lx % bx and Ly % by must be 0";
+  return nullptr;
+}
+
+// The wipe rule makes the trajectory depend on the window, so it needs a
+// window fixed by the caller (a tuned one adapts to measured iterations).
+static const char* check_step_rule(int rule, bool tuned_window) {
+  if (rule != SR_STEP_CONTINUE && rule != SR_STEP_WIPE) return "unknown step rule";
+  if (rule == SR_STEP_WIPE && tuned_window) return "the wipe step rule needs a fixed window (window > 0)";
   return nullptr;
 }
 
@@ -268,6 +278,7 @@ static int resolve(sr_params& p, bool& tuned_window, std::string& why) {
   }
   if (const char* w = check_block(p.Lx, p.Ly, p.bx, p.by)) { why = w; return SR_EINVAL; }
   if (!(p.window > 0.0) || !std::isfinite(p.window)) { why = "window must be > 0"; return SR_EINVAL; }
+  if (const char* w = check_step_rule(p.step_rule, tuned_window)) { why = w; return SR_EINVAL; }
   return SR_OK;
 }
 
@@ -288,6 +299,7 @@ static int create_impl(const sr_params* pin, void* stream, sr_sim** out, bool in
   if (p.init != SR_INIT_RANDOM && p.init != SR_INIT_ALL_UP && p.init != SR_INIT_USER)
     SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "unknown init mode");
   const bool tuned_window = (p.window == 0.0);
+  if (const char* why = check_step_rule(p.step_rule, tuned_window)) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "%s", why);
   if (p.bx == 0 || p.by == 0 || p.window == 0.0) {
     int32_t tbx, tby; double tw;
     if (sr_tune(&p, &tbx, &tby, &tw) != SR_OK) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "tuner found no block");
@@ -319,6 +331,7 @@ static int create_impl(const sr_params* pin, void* stream, sr_sim** out, bool in
   L.sshift = sites_per_lane_shift(p.bx * p.by);
   L.S = 1 << L.sshift;
   L.tick_bits = p.tick_bits;
+  L.wipe = p.step_rule == SR_STEP_WIPE ? 1 : 0;
   if (rate_table(p.J, p.h, p.T, p.rule, L.rate) != 0) { delete s; SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "bad rate parameters"); }
   L.seed_lo = (uint32_t)p.seed; L.seed_hi = (uint32_t)(p.seed >> 32);
   if (s->tune) s->Wmax = std::max(s->Wmin, std::min(s->Wmax, 4 * W));
@@ -691,7 +704,7 @@ extern "C" int sr_save(sr_sim* s, void* blob, size_t cap, size_t* n) {
   if (cap < need) SR_FAIL(s, SR_EINVAL, "checkpoint buffer too small (%zu < %zu)", cap, need);
   SaveHeader h;
   std::memset(&h, 0, sizeof(h));
-  std::memcpy(h.magic, "SRCKPT2", 8);
+  std::memcpy(h.magic, "SRCKPT3", 8);
   h.p = s->p;
   h.p.init_spins = nullptr;
   sr_obs o;
@@ -719,7 +732,7 @@ extern "C" int sr_load(const void* blob, size_t n, void* stream, sr_sim** out) {
   *out = nullptr;
   SaveHeader h;
   std::memcpy(&h, blob, sizeof(h));
-  if (std::memcmp(h.magic, "SRCKPT2", 8) != 0) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "not a checkpoint");
+  if (std::memcmp(h.magic, "SRCKPT3", 8) != 0) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "not a checkpoint");
   if (h.p.Lx < 4 || h.p.Ly < 4 || h.nsub <= 0) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "bad checkpoint header");
   size_t nsite = (size_t)h.p.Lx * h.p.Ly;
   size_t need = sizeof(h) + nsite + (size_t)h.nsub * sizeof(Carry) + (h.has_init ? nsite : 0);
@@ -779,11 +792,45 @@ extern "C" int sr_batch_run(sr_sim* const* sims, int32_t n, void* stream_) {
   return sr_batch_step(sims, n, -1, stream_);
 }
 
-extern "C" int sr_batch_step(sr_sim* const* sims, int32_t n, int32_t max_windows, void* stream_) {
+// Device memory of one persistent launch, carved from one block: lattice
+// descriptors, per-lattice run records, per-(lattice, shard) task counts, the
+// queue counters and the kShards task rings.  Regions start on 256-byte
+// boundaries, so the ones that must start zeroed (counts, counters, rings)
+// are cleared by one kernel over a contiguous range.
+struct BatchLayout {
+  size_t lat, run, rem, ctr, q, total;
+};
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+static BatchLayout batch_layout(int m, uint64_t qn) {
+  BatchLayout b;
+  b.lat = 0;
+  b.run = align256(b.lat + (size_t)m * sizeof(Lattice));
+  b.rem = align256(b.run + (size_t)m * sizeof(LatRun));
+  b.ctr = align256(b.rem + (size_t)m * kShards * sizeof(ShardRem));
+  b.q = align256(b.ctr + sizeof(BatchCounters));
+  b.total = align256(b.q + (size_t)kShards * qn * sizeof(unsigned long long));
+  return b;
+}
+
+// Host staging of one launch: caller-provided arrays of `cap` entries.
+struct BatchStage {
+  Lattice* lat;
+  LatRun* run;
+  int* idx;
+  int cap;
+};
+
+// One persistent launch over the listed simulations (sr_batch_step).  `dev`
+// = nullptr: the launch's device memory is allocated here and freed after;
+// otherwise it is the caller's block of `dev_cap` bytes, nothing is
+// allocated, and a lattice whose buffers overflow ends the call with
+// SR_EOVERFLOW instead of being re-run with grown buffers.
+static int batch_core(sr_sim* const* sims, int32_t n, int32_t max_windows, hipStream_t stream,
+                      BatchStage& hs, void* dev, size_t dev_cap) {
+  const bool fixed_mem = dev != nullptr;
   if (!sims || n <= 0) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "sr_batch_run needs simulations");
   if (n > 4096) SR_FAIL(sims[0], SR_EINVAL, "at most 4096 lattices per batch");
-  hipStream_t stream = (hipStream_t)stream_;
-  std::vector<int> idx;
+  int m = 0;
   size_t lds = 16;
   uint64_t total = 0;
   for (int i = 0; i < n; ++i) {
@@ -792,16 +839,16 @@ extern "C" int sr_batch_step(sr_sim* const* sims, int32_t n, int32_t max_windows
     if (s->p.log_mode != SR_LOG_DIGEST) SR_FAIL(s, SR_EINVAL, "batched runs keep digests only (SR_LOG_DIGEST)");
     if (s->L.nsub >= (1 << 20)) SR_FAIL(s, SR_EINVAL, "too many subdomains for the batch queue");
     if (s->st.t_c >= s->H) continue;
-    idx.push_back(i);
+    if (m >= hs.cap) SR_FAIL(s, SR_EINVAL, "at most %d lattices per batch here", hs.cap);
+    hs.idx[m++] = i;
     lds = std::max(lds, relax_lds(s->L));
     total += (uint64_t)s->L.nsub;
   }
-  if (idx.empty()) return SR_OK;
-  sr_sim* s0 = sims[idx[0]];
-  int m = (int)idx.size();
-  int dev = 0, ncu = 0;
-  HIP_OR_FAIL(s0, hipGetDevice(&dev));
-  HIP_OR_FAIL(s0, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  if (m == 0) return SR_OK;
+  sr_sim* s0 = sims[hs.idx[0]];
+  int dev_id = 0, ncu = 0;
+  HIP_OR_FAIL(s0, hipGetDevice(&dev_id));
+  HIP_OR_FAIL(s0, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev_id));
   int per_cu = batch_waves_per_cu(lds);
   if (per_cu <= 0) SR_FAIL(s0, SR_EDEVICE, "cannot size the persistent grid");
   int waves = std::max(per_cu * ncu, kShards);   // every shard needs a wave
@@ -809,78 +856,58 @@ extern "C" int sr_batch_step(sr_sim* const* sims, int32_t n, int32_t max_windows
   // (tasks are dealt round-robin, at most one extra per lattice) plus the
   // tickets its waves may hold ahead of production
   uint64_t qn = 1;
-  while (qn < total / kShards + (uint64_t)idx.size() + (uint64_t)waves / kShards + 64) qn <<= 1;
-
-  std::vector<Lattice> lat(m);
-  std::vector<LatRun> run(m);
-  std::vector<unsigned long long> q(kShards * qn, 0ull);
-  std::vector<ShardRem> rem((size_t)m * kShards);
-  std::memset(rem.data(), 0, rem.size() * sizeof(ShardRem));
-  uint64_t fill[kShards] = {};
+  while (qn < total / kShards + (uint64_t)m + (uint64_t)waves / kShards + 64) qn <<= 1;
+  const BatchLayout bl = batch_layout(m, qn);
+  char* base = (char*)dev;
+  if (fixed_mem) {
+    if (bl.total > dev_cap)
+      SR_FAIL(s0, SR_EINVAL, "this batch needs %zu bytes of launch memory, more than the %zu available "
+              "(fewer lattices or subdomains per call)", bl.total, dev_cap);
+  } else if (hipMalloc((void**)&base, bl.total) != hipSuccess) {
+    SR_FAIL(s0, SR_ENOMEM, "cannot allocate the batch queue");
+  }
+  auto release = [&]() {
+    if (!fixed_mem) (void)hipFree(base);
+  };
+  Lattice* dlat = (Lattice*)(base + bl.lat);
+  LatRun* drun = (LatRun*)(base + bl.run);
+  ShardRem* drem = (ShardRem*)(base + bl.rem);
+  BatchCounters* dctr = (BatchCounters*)(base + bl.ctr);
+  unsigned long long* dq = (unsigned long long*)(base + bl.q);
   for (int k = 0; k < m; ++k) {
-    sr_sim* s = sims[idx[k]];
-    lat[k] = s->L;
-    lat[k].need = s->need;
-    lat[k].ckint = kCkIntBatch;
-    HIP_OR_FAIL(s0, hipMemsetAsync(s->need, 0, 2 * (size_t)need_stride(s->L.nsub), stream));
-    LatRun& r = run[k];
+    sr_sim* s = sims[hs.idx[k]];
+    hs.lat[k] = s->L;
+    hs.lat[k].need = s->need;
+    hs.lat[k].ckint = kCkIntBatch;
+    if (hipMemsetAsync(s->need, 0, 2 * (size_t)need_stride(s->L.nsub), stream) != hipSuccess) {
+      release();
+      SR_FAIL(s0, SR_EDEVICE, "clearing run marks failed");
+    }
+    LatRun& r = hs.run[k];
     std::memset(&r, 0, sizeof(r));
     r.st = s->st;
     r.st.it = 0; r.st.fi = 0;
     r.st.t_end = std::min(s->st.t_c + s->W, s->H);
     r.H = s->H; r.W = s->W;
-    r.shards_left = std::min(s->L.nsub, kShards);
     r.max_iters = s->p.max_iters;
     r.status = kRunning;
-    r.tasks = s->L.nsub;
     r.tune = s->tune ? 1 : 0;
     r.win_budget = max_windows > 0 ? max_windows : -1;
     r.Wmin = s->Wmin; r.Wmax = s->Wmax;
-    // the first iteration runs every subdomain: task d goes to shard
-    // (k + d) % kShards, as the device decider deals later iterations
-    for (int d = 0; d < s->L.nsub; ++d) {
-      const int g = (k % kShards + d) % kShards;
-      const uint64_t at = fill[g]++;
-      q[(size_t)g * qn + at] = ((unsigned long long)(at + 1) << 32) | ((unsigned long long)k << 20) | (unsigned)d;
-      rem[(size_t)k * kShards + g].n++;
-    }
+    // the first iteration's tasks, their per-shard counts and shards_left
+    // are dealt by the kernel itself
   }
-  Lattice* dlat = nullptr;
-  LatRun* drun = nullptr;
-  unsigned long long* dq = nullptr;
-  BatchCounters* dctr = nullptr;
-  ShardRem* drem = nullptr;
-  auto release = [&]() {
-    if (dlat) (void)hipFree(dlat);
-    if (drun) (void)hipFree(drun);
-    if (dq) (void)hipFree(dq);
-    if (dctr) (void)hipFree(dctr);
-    if (drem) (void)hipFree(drem);
-  };
-  if (hipMalloc(&dlat, m * sizeof(Lattice)) != hipSuccess || hipMalloc(&drun, m * sizeof(LatRun)) != hipSuccess ||
-      hipMalloc(&dq, q.size() * sizeof(unsigned long long)) != hipSuccess ||
-      hipMalloc(&dctr, sizeof(BatchCounters)) != hipSuccess ||
-      hipMalloc(&drem, rem.size() * sizeof(ShardRem)) != hipSuccess) {
-    release();
-    SR_FAIL(s0, SR_ENOMEM, "cannot allocate the batch queue");
-  }
-  BatchCounters ctr;
-  std::memset(&ctr, 0, sizeof(ctr));
-  for (int g = 0; g < kShards; ++g) { ctr.sh[g].head = 0; ctr.sh[g].tail = fill[g]; }
-  ctr.done = 0;
   BatchArgs args;
   args.ctr = dctr; args.q = dq; args.lat = dlat; args.run = drun; args.rem = drem;
   args.nlat = (uint32_t)m; args.qmask = (uint32_t)(qn - 1);
   hipEvent_t e0 = s0->ev[0], e1 = s0->ev[1];
-  int rc = SR_OK;
-  if (hipMemcpyAsync(dlat, lat.data(), m * sizeof(Lattice), hipMemcpyHostToDevice, stream) != hipSuccess ||
-      hipMemcpyAsync(drun, run.data(), m * sizeof(LatRun), hipMemcpyHostToDevice, stream) != hipSuccess ||
-      hipMemcpyAsync(dq, q.data(), q.size() * sizeof(unsigned long long), hipMemcpyHostToDevice, stream) != hipSuccess ||
-      hipMemcpyAsync(drem, rem.data(), rem.size() * sizeof(ShardRem), hipMemcpyHostToDevice, stream) != hipSuccess ||
-      hipMemcpyAsync(dctr, &ctr, sizeof(ctr), hipMemcpyHostToDevice, stream) != hipSuccess ||
+  BatchCounters ctr;
+  if (launch_zero(base + bl.rem, bl.total - bl.rem, stream) != hipSuccess ||
+      hipMemcpyAsync(dlat, hs.lat, m * sizeof(Lattice), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(drun, hs.run, m * sizeof(LatRun), hipMemcpyHostToDevice, stream) != hipSuccess ||
       hipEventRecord(e0, stream) != hipSuccess || launch_batch(args, waves, lds, stream) != hipSuccess ||
       hipEventRecord(e1, stream) != hipSuccess ||
-      hipMemcpyAsync(run.data(), drun, m * sizeof(LatRun), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipMemcpyAsync(hs.run, drun, m * sizeof(LatRun), hipMemcpyDeviceToHost, stream) != hipSuccess ||
       hipMemcpyAsync(&ctr, dctr, sizeof(ctr), hipMemcpyDeviceToHost, stream) != hipSuccess ||
       hipStreamSynchronize(stream) != hipSuccess) {
     release();
@@ -889,10 +916,10 @@ extern "C" int sr_batch_step(sr_sim* const* sims, int32_t n, int32_t max_windows
   float ms = 0.f;
   (void)hipEventElapsedTime(&ms, e0, e1);
   release();
-  std::string first_err;
+  int rc = SR_OK, first_bad = -1;
   for (int k = 0; k < m; ++k) {
-    sr_sim* s = sims[idx[k]];
-    const LatRun& r = run[k];
+    sr_sim* s = sims[hs.idx[k]];
+    const LatRun& r = hs.run[k];
     s->st.t_c = r.st.t_c;
     s->st.wp = r.st.wp;
     s->W = r.W;
@@ -904,12 +931,18 @@ extern "C" int sr_batch_step(sr_sim* const* sims, int32_t n, int32_t max_windows
     s->batch_tasks += r.tasks;
     int one = SR_OK;
     if (r.status == kOverflow) {
-      // grow what overflowed (the decider leaves that iteration's flags in
-      // the lattice record), then run this step's windows alone from the
-      // last committed one
+      // the decider leaves that iteration's flags in the lattice record
       uint32_t bits = (r.fl.ovf_hist ? 1u : 0u) | (r.fl.ovf_log ? 2u : 0u);
-      one = grow(s, bits ? bits : 3u);
-      if (one == SR_OK) one = sr_run_window(s, max_windows > 0 ? max_windows : -1, nullptr, nullptr);
+      if (fixed_mem) {
+        // growing the buffers would allocate: the window stays uncommitted
+        one = SR_EOVERFLOW;
+        s->err = "a boundary list or window log overflowed (growing it needs an allocation)";
+      } else {
+        // grow what overflowed, then run this step's windows alone from the
+        // last committed one
+        one = grow(s, bits ? bits : 3u);
+        if (one == SR_OK) one = sr_run_window(s, max_windows > 0 ? max_windows : -1, nullptr, nullptr);
+      }
     } else if (r.status == kNoConv) {
       one = SR_ENOCONV;
       s->err = "window did not converge within max_iters (batched run)";
@@ -919,16 +952,26 @@ extern "C" int sr_batch_step(sr_sim* const* sims, int32_t n, int32_t max_windows
                (ctr.abort ? ", the persistent kernel gave up waiting for work)" : ")");
     }
     s->failed = one;
-    if (one != SR_OK && rc == SR_OK) {
-      rc = one;
-      char b[256];
-      std::snprintf(b, sizeof(b), "lattice %d of the batch (status %d): %s", idx[k], r.status, s->err.c_str());
-      first_err = b;
-    }
+    if (one != SR_OK && rc == SR_OK) { rc = one; first_bad = k; }
   }
-  if (rc != SR_OK) for (int k = 0; k < m; ++k) sims[idx[k]]->err = first_err;
+  if (rc != SR_OK) {
+    char b[320];
+    sr_sim* bad = sims[hs.idx[first_bad]];
+    std::snprintf(b, sizeof(b), "lattice %d of the batch (status %d): %s", hs.idx[first_bad],
+                  hs.run[first_bad].status, bad->err.c_str());
+    for (int k = 0; k < m; ++k) sims[hs.idx[k]]->err = b;
+  }
   s0->last_batch_ms = ms;
   return rc;
+}
+
+extern "C" int sr_batch_step(sr_sim* const* sims, int32_t n, int32_t max_windows, void* stream_) {
+  if (!sims || n <= 0) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "sr_batch_run needs simulations");
+  std::vector<Lattice> lat((size_t)n);
+  std::vector<LatRun> run((size_t)n);
+  std::vector<int> idx((size_t)n);
+  BatchStage hs{lat.data(), run.data(), idx.data(), n};
+  return batch_core(sims, n, max_windows, (hipStream_t)stream_, hs, nullptr, 0);
 }
 
 // ------------------------------------------------------------ serving

@@ -83,6 +83,8 @@ struct Lattice {
   uint32_t seed_lo, seed_hi;
   int32_t hcap;           // entries per boundary list
   int32_t wcap;           // entries per subdomain window log
+  int32_t wipe;           // step rule: 1 = every window start t_c > 0 drops
+                          // the pending pair (wipe the slate, Sec. 5)
   // Double buffers are single allocations; buffer q starts at base + q * stride.
   int8_t* spins;          // 2 x Lx*Ly: committed lattice, by window parity
   Carry* carry;           // 2 x nsub: by window parity

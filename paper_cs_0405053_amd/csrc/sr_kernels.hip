@@ -398,6 +398,11 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
       if (lane == k) ncnt = tot;
     }
     j = cin->j; acc = cin->acc; anchor = cin->anchor; dtot = 0;
+    if (L.wipe && st.t_c > 0) {
+      // wipe the slate (Sec. 5): the pending pair is dropped, the next one
+      // starts its hazard at the window start
+      j += 1; acc = 0; anchor = st.t_c;
+    }
     nev = 0; nbound = 0;
 #pragma unroll
     for (int e = 0; e < 4; ++e) n0[e] = 0;
@@ -1064,6 +1069,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void ba
   const int g = (int)(blockIdx.x % kShards);
   ShardCtr* sc = &B.ctr->sh[g];
   const unsigned long long* qg = B.q + (size_t)g * ((size_t)B.qmask + 1);
+  // the first iteration of every lattice (all its subdomains) is dealt by
+  // the grid before any wave takes a ticket; tasks are taken as they appear
+  for (int k = blockIdx.x; k < (int)B.nlat; k += gridDim.x)
+    enqueue_iteration(B, k, &B.run[k], lats[k], 0, lane);
   unsigned long long t = 0;
   if (lane == 0) t = atomicAdd(&sc->head, 1ull);
   t = ((uint64_t)rdl((uint32_t)(t >> 32), 0) << 32) | rdl((uint32_t)t, 0);
@@ -1237,6 +1246,23 @@ hipError_t build_window_graph(const Lattice& L, const Step* dstep, int k, hipGra
   if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   return e;
+}
+
+// Zeroes `bytes` (a multiple of 16) at a 16-byte aligned address: a kernel,
+// so that no memset is issued for the batch queue.
+__global__ void zero_kernel(uint4* p, size_t n16) {
+  const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = z;
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t stream) {
+  const size_t n16 = bytes / 16;
+  if (n16 == 0) return hipSuccess;
+  size_t blocks = (n16 + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, (uint4*)p, n16);
+  return hipGetLastError();
 }
 
 hipError_t launch_batch(const BatchArgs& B, int waves, size_t lds, hipStream_t stream) {

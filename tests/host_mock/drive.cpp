@@ -9,6 +9,7 @@
 #include "../../include/sr.h"
 
 extern "C" size_t sr_mock_live_allocations();
+extern "C" size_t sr_mock_malloc_calls();
 
 #define CHECK(c)                                                              \
   do {                                                                        \

@@ -10,6 +10,8 @@
 #define __device__
 #define __global__
 #define __forceinline__ inline
+#define __align__(n) __attribute__((aligned(n)))
+#define HIP_SYMBOL(x) ((const void*)&(x))
 typedef int hipError_t;
 enum { hipSuccess = 0, hipErrorOutOfMemory = 2 };
 typedef struct ihipStream_t* hipStream_t;
@@ -41,4 +43,5 @@ hipError_t hipGetLastError();
 hipError_t hipGetDevice(int*);
 hipError_t hipDeviceGetAttribute(int*, hipDeviceAttribute_t, int);
 hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t);
+hipError_t hipGetSymbolAddress(void** p, const void* symbol);
 hipError_t hipGraphExecDestroy(hipGraphExec_t);

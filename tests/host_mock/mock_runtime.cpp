@@ -18,6 +18,7 @@
 
 static std::set<void*> g_dev, g_host, g_ev;
 static std::mutex g_mu;   // the stand-in runtime may be called from several threads
+static size_t g_malloc_calls = 0;
 
 static int env_int(const char* name, int dflt) {
   const char* v = std::getenv(name);
@@ -27,6 +28,7 @@ static int env_int(const char* name, int dflt) {
 hipError_t hipMalloc(void** p, size_t n) {
   *p = std::calloc(1, n ? n : 1);
   std::lock_guard<std::mutex> g(g_mu);
+  g_malloc_calls++;
   g_dev.insert(*p);
   return hipSuccess;
 }
@@ -75,6 +77,11 @@ hipError_t hipEventElapsedTime(float* ms, hipEvent_t, hipEvent_t) { *ms = 0.01f;
 const char* hipGetErrorString(hipError_t) { return "host stand-in error"; }
 hipError_t hipGetLastError() { return hipSuccess; }
 hipError_t hipGetDevice(int* d) { *d = 0; return hipSuccess; }
+// a __device__ array is a host array here: its "device address" is itself
+hipError_t hipGetSymbolAddress(void** p, const void* symbol) {
+  *p = const_cast<void*>(symbol);
+  return hipSuccess;
+}
 hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t, int) { *v = 256; return hipSuccess; }
 
 // A "graph" of k relaxation iterations: remembers the lattice descriptor and
@@ -104,6 +111,11 @@ hipError_t hipGraphLaunch(hipGraphExec_t g, hipStream_t) {
 hipError_t hipGraphExecDestroy(hipGraphExec_t g) {
   delete g;
   return hipSuccess;
+}
+
+extern "C" size_t sr_mock_malloc_calls() {
+  std::lock_guard<std::mutex> g(g_mu);
+  return g_malloc_calls;
 }
 
 extern "C" size_t sr_mock_live_allocations() {
@@ -161,6 +173,10 @@ hipError_t launch_batch(const BatchArgs& B, int, size_t, hipStream_t) {
     }
     B.ctr->done++;
   }
+  return hipSuccess;
+}
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t) {
+  std::memset(p, 0, bytes);
   return hipSuccess;
 }
 int batch_waves_per_cu(size_t) { return 4; }

@@ -50,11 +50,20 @@ def test_one_hip_runtime_per_process():
     dict(bx=32, by=48, Ly=96),   # bx*by > 1024
     dict(Lx=128, bx=128, by=4),  # bx > 64
     dict(init="user"),           # no spins given
+    dict(step="wipe", window=0.0),   # wipe rule with a tuned window
+    dict(step=7),                # unknown step rule
 ])
 def test_invalid_parameters_rejected(bad):
     import paper_cs_0405053_amd as sr
     p = dict(Lx=64, Ly=64, bx=16, by=16, T=1.5, h=0.0, window=1.0, horizon=5.0, seed=1)
     p.update(bad)
+    if p.get("step") == 7:
+        import ctypes
+        cp, _ = sr.to_params(dict(p, step="continue"))
+        cp.step_rule = 7
+        h = ctypes.c_void_p()
+        assert sr.lib().sr_create(ctypes.byref(cp), None, ctypes.byref(h)) == sr.SR_EINVAL
+        return
     if p.get("rule") == 5:
         p["rule"] = 1
         p["T"] = -1.0
@@ -70,3 +79,17 @@ def test_tuner_block_is_deterministic_and_valid():
             bx, by, w = sr.tune(dict(Lx=L, Ly=L, T=T, horizon=10.0))
             assert L % bx == 0 and L % by == 0 and w > 0
             assert (bx, by, w) == sr.tune(dict(Lx=L, Ly=L, T=T, horizon=10.0))
+
+
+def test_tuner_block_matches_stated_workload_block():
+    # stored oracle results of tuned workloads use workloads.tuned_block
+    import paper_cs_0405053_amd as sr
+    import workloads as W
+    ps = W.batch() + W.serve_stream(n=256)
+    for p in ps:
+        bx, by, _ = sr.tune(p)
+        assert (bx, by) == W.tuned_block(p["Lx"], p["Ly"], p["T"]), p
+    for L in (32, 48, 64, 80, 96, 1000, 2048, 4096):
+        for T in (1.0, 1.25, 1.3, 3.0):
+            bx, by, _ = sr.tune(dict(Lx=L, Ly=L, T=T, horizon=1.0))
+            assert (bx, by) == W.tuned_block(L, L, T), (L, T)

@@ -169,3 +169,17 @@ def test_batch_no_convergence_reports():
         sr.batch_run([s])
     assert e.value.code == sr.SR_ENOCONV
     assert s.observables()["tick"] == 0
+
+
+def test_batched_wipe_step_rule_equals_oracle():
+    # the wipe rule inside the persistent kernel (window starts by the decider)
+    sr = _sr()
+    ps = [dict(p, step="wipe") for p in mix(n=6, horizon=3.0, seed=11)]
+    sims = [sr.Sim(p) for p in ps]
+    sr.batch_run(sims)
+    for p, s in zip(ps, sims):
+        ref = oracle.des(p, log=False)
+        assert np.array_equal(s.spins(), ref["spins"]), p
+        assert np.array_equal(s.digests()[0], ref["sub_digest"]), p
+        assert np.array_equal(s.carry(), ref["carry"][:, :3]), p
+        s.close()

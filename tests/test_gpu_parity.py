@@ -292,3 +292,31 @@ def test_checkpoint_user_start_and_tuned_window():
         assert np.array_equal(a.spins(), c.spins())
         a.close()
         c.close()
+
+
+# the wipe-the-slate step rule (Sec. 5): every window start drops the
+# pending events, so the trajectory depends on the window; the oracle's DES
+# and literal relaxation apply the same rule
+WIPE_CASES = [
+    (32, 32, 16, 16, 2.5, 0.1, 0.5, 4.0, 28, "metropolis", "random"),     # 16x16, no wrap
+    (64, 64, 32, 32, 2.269, 0.05, 0.25, 2.0, 28, "metropolis", "random"),  # 32x32
+    (32, 16, 8, 4, 2.5, -0.2, 1.0, 5.0, 28, "glauber", "random"),         # runtime shape
+    (16, 16, 16, 16, 2.0, 0.1, 0.5, 5.0, 28, "metropolis", "random"),     # one subdomain, wraps
+    (32, 32, 8, 8, 2.0, 0.0, 0.25, 3.1, 4, "metropolis", "random"),       # ties, ragged horizon
+    (32, 32, 16, 16, 1.0, 0.05, 0.5, 6.0, 28, "metropolis", "up"),        # sparse
+]
+
+
+@pytest.mark.parametrize("Lx,Ly,bx,by,T,h,win,hor,tb,rule,init", WIPE_CASES)
+def test_wipe_step_rule_matches_oracle(Lx, Ly, bx, by, T, h, win, hor, tb, rule, init):
+    p = W.params(Lx, Ly, bx, by, T=T, h=h, window=win, horizon=hor, seed=4321 + Lx + bx,
+                 tick_bits=tb, rule=rule, init=init, step="wipe")
+    check_against_oracle(p)
+
+
+def test_wipe_step_rule_one_launch_per_iteration(monkeypatch):
+    monkeypatch.setenv("SR_NO_GRAPHS", "1")
+    Lx, Ly, bx, by, T, h, win, hor, tb, rule, init = WIPE_CASES[0]
+    p = W.params(Lx, Ly, bx, by, T=T, h=h, window=win, horizon=hor, seed=77,
+                 tick_bits=tb, rule=rule, init=init, step="wipe")
+    check_against_oracle(p)
