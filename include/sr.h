@@ -215,6 +215,24 @@ int sr_batch_run(sr_sim* const* sims, int32_t n, void* hip_stream);
  * simulations may be added to or removed from the list. */
 int sr_batch_step(sr_sim* const* sims, int32_t n, int32_t max_windows, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * step as sr_batch_step, bit-identical results, but the persistent launch's
+ * queue, counters, lattice descriptors and per-lattice records live in one
+ * 8 MiB array of device memory per GPU that the library holds for the life
+ * of the process; the call allocates and frees no device memory (and, on
+ * success, no host memory).  Limits: at most 1024 lattices with unfinished
+ * windows per call, and the call's queue must fit the array (about 500 000
+ * subdomains in all); SR_EINVAL otherwise, before any device work.  A
+ * lattice whose boundary list or window log overflows is not re-run with
+ * grown buffers (that would allocate): the call returns SR_EOVERFLOW and the
+ * window stays uncommitted (sr_batch_step or sr_run_window can continue it).
+ * Every call on one GPU uses that GPU's one array and the next call
+ * overwrites it, so calls that overlapped on one GPU would race: the library
+ * serialises them within a process (a mutex held for the whole call).  Each
+ * process has its own arrays. */
+int sr_batch_step_static(sr_sim* const* sims, int32_t n, int32_t max_windows, void* hip_stream);
+
 /* ---- tuner ---- block and first window for a lattice (used when bx = by =
  * 0 or window = 0).  Block: a fixed table over (L, T) -- never load-dependent,
  * because the block partition keys the random streams and so the trajectory.

@@ -35,7 +35,7 @@ EXPORTS = ["sr_create", "sr_run_window", "sr_observables", "sr_destroy", "sr_get
            "sr_get_log", "sr_get_digests", "sr_get_carry", "sr_get_rate_table", "sr_rate_table",
            "sr_save",
            "sr_load", "sr_last_error", "sr_batch_run", "sr_tune", "sr_reset",
-           "sr_batch_step", "sr_server_create", "sr_server_submit", "sr_server_pump",
+           "sr_batch_step", "sr_batch_step_static", "sr_server_create", "sr_server_submit", "sr_server_pump",
            "sr_server_poll", "sr_server_stats", "sr_server_destroy"]
 
 
@@ -119,6 +119,7 @@ def lib() -> C.CDLL:
         L.sr_batch_run.argtypes = [P, C.c_int32, P]
         L.sr_reset.argtypes = [P]
         L.sr_batch_step.argtypes = [P, C.c_int32, C.c_int32, P]
+        L.sr_batch_step_static.argtypes = [P, C.c_int32, C.c_int32, P]
         L.sr_server_create.argtypes = [C.c_size_t, C.c_int32, P, C.POINTER(P)]
         L.sr_server_submit.argtypes = [P, C.POINTER(Params), C.POINTER(C.c_uint64)]
         L.sr_server_pump.argtypes = [P, C.POINTER(C.c_int32)]
@@ -322,6 +323,15 @@ def batch_step(sims: Sequence[Sim], max_windows: int, stream=None) -> None:
     rc = lib().sr_batch_step(arr, len(sims), max_windows, _stream_ptr(stream))
     if rc != SR_OK:
         raise SRError(rc, "sr_batch_step: " + last_error(sims[0].handle if sims else None))
+
+
+def batch_step_static(sims: Sequence[Sim], max_windows: int, stream=None) -> None:
+    """batch_step without any device allocation: the launch's queue and
+    records live in the library's fixed per-GPU array (sr_batch_step_static)."""
+    arr = (C.c_void_p * len(sims))(*[s.handle for s in sims])
+    rc = lib().sr_batch_step_static(arr, len(sims), max_windows, _stream_ptr(stream))
+    if rc != SR_OK:
+        raise SRError(rc, "sr_batch_step_static: " + last_error(sims[0].handle if sims else None))
 
 
 def batch_run(sims: Sequence[Sim], stream=None) -> None:

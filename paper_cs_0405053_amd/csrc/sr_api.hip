@@ -974,6 +974,40 @@ extern "C" int sr_batch_step(sr_sim* const* sims, int32_t n, int32_t max_windows
   return batch_core(sims, n, max_windows, (hipStream_t)stream_, hs, nullptr, 0);
 }
 
+// ------------------------------------------------------------ no-allocation batch step
+// The launch memory of sr_batch_step_static: one array per GPU, kept for the
+// life of the process.  In host code `scratch` names a host-side stand-in;
+// its device address on the current GPU comes from hipGetSymbolAddress, taken
+// once per device, and only that address is ever passed on.
+constexpr size_t kStaticScratchBytes = (size_t)8 << 20;
+constexpr int kStaticMaxLattices = 1024;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_static_mu;                  // serialises sr_batch_step_static calls
+static void* g_scratch_ptr[kMaxDevices];        // device address of `scratch`, per GPU
+static Lattice g_static_lat[kStaticMaxLattices]; // host staging (no allocation per call)
+static LatRun g_static_run[kStaticMaxLattices];
+static int g_static_idx[kStaticMaxLattices];
+
+extern "C" int sr_batch_step_static(sr_sim* const* sims, int32_t n, int32_t max_windows, void* stream_) {
+  if (!sims || n <= 0) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "sr_batch_step_static needs simulations");
+  std::lock_guard<std::mutex> guard(g_static_mu);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    SR_FAIL(sims[0], SR_EDEVICE, "no usable current device");
+  if (!g_scratch_ptr[dev]) {
+    // first call on this GPU (current): the device address of its copy
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      SR_FAIL(sims[0], SR_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  BatchStage hs{g_static_lat, g_static_run, g_static_idx, kStaticMaxLattices};
+  return batch_core(sims, n, max_windows, (hipStream_t)stream_, hs, g_scratch_ptr[dev], kStaticScratchBytes);
+}
+
 // ------------------------------------------------------------ serving
 // Continuous batching, driven by the caller.  sr_server_submit queues a
 // request; every sr_server_pump is one scheduling round: admit queued

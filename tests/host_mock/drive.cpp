@@ -122,6 +122,52 @@ static void batch() {
   for (sr_sim* s : sims) sr_destroy(s);
 }
 
+// The no-allocation batch step: no device allocation or free inside the call,
+// two calls in a row (the second on fewer lattices) reuse the one array, an
+// overflow is reported instead of regrown, too many lattices are refused.
+static void static_step() {
+  std::vector<sr_sim*> sims;
+  for (int i = 0; i < 5; ++i) {
+    sr_params p = params(32 + 16 * i, i % 2 ? 0.0 : 0.5, 2.0 + i, 300 + i);
+    sr_sim* s = nullptr;
+    CHECK(sr_create(&p, nullptr, &s) == SR_OK);
+    sims.push_back(s);
+  }
+  const char* ovf = std::getenv("SR_MOCK_OVERFLOW");
+  const size_t calls = sr_mock_malloc_calls();
+  const size_t live = sr_mock_live_allocations();
+  if (ovf && std::atoi(ovf)) {
+    CHECK(sr_batch_step_static(sims.data(), 5, 2, nullptr) == SR_EOVERFLOW);
+    CHECK(sr_mock_malloc_calls() == calls && sr_mock_live_allocations() == live);
+    for (sr_sim* s : sims) sr_destroy(s);
+    return;
+  }
+  CHECK(sr_batch_step_static(sims.data(), 5, 2, nullptr) == SR_OK);
+  CHECK(sr_batch_step_static(sims.data() + 3, 2, -1, nullptr) == SR_OK);
+  CHECK(sr_mock_malloc_calls() == calls && sr_mock_live_allocations() == live);
+  sr_obs o;
+  for (int i = 0; i < 5; ++i) {
+    CHECK(sr_observables(sims[i], &o) == SR_OK);
+    if (i < 3) CHECK(o.windows >= 1 && o.windows <= 2);
+    else CHECK(o.tick == o.horizon_ticks);
+  }
+  CHECK(sr_batch_step_static(sims.data(), 5, -1, nullptr) == SR_OK);
+  for (sr_sim* s : sims) CHECK(sr_observables(s, &o) == SR_OK && o.tick == o.horizon_ticks);
+  for (sr_sim* s : sims) sr_destroy(s);
+  // more lattices than the array's record space: refused before device work
+  std::vector<sr_sim*> many;
+  for (int i = 0; i < 1025; ++i) {
+    sr_params p = params(8, 0.5, 1.0, 900 + i);
+    p.bx = p.by = 4;
+    sr_sim* s = nullptr;
+    CHECK(sr_create(&p, nullptr, &s) == SR_OK);
+    many.push_back(s);
+  }
+  CHECK(sr_batch_step_static(many.data(), 1025, -1, nullptr) == SR_EINVAL);
+  CHECK(sr_batch_step_static(many.data(), 1024, -1, nullptr) == SR_OK);
+  for (sr_sim* s : many) sr_destroy(s);
+}
+
 // Save / load round trip and argument errors.
 static void errors() {
   sr_params p = params(64, 0.5, 2.0, 5);
@@ -229,6 +275,7 @@ int main(int argc, char** argv) {
   else if (!std::strcmp(w, "batch")) batch();
   else if (!std::strcmp(w, "errors")) errors();
   else if (!std::strcmp(w, "threads")) threads();
+  else if (!std::strcmp(w, "static")) static_step();
   else return 2;
   CHECK(sr_mock_live_allocations() == 0);
   std::printf("ok %s\n", w);

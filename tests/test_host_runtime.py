@@ -82,6 +82,11 @@ def test_batch_log_overflow_at_list_capacity_limit(drive):
     run(drive, "batch", SR_MOCK_G=4, SR_MOCK_OVERFLOW=2)
 
 
+@pytest.mark.parametrize("overflow", [0, 1])
+def test_static_batch_step_allocates_nothing(drive, overflow):
+    run(drive, "static", SR_MOCK_G=3, SR_MOCK_OVERFLOW=overflow)
+
+
 def test_checkpoint_and_argument_errors(drive):
     run(drive, "errors")
 
