@@ -14,6 +14,10 @@ Entry points:
                                 converged synchronous relaxation reproduces.
 * ``sr(p)``                     literal Jacobi synchronous relaxation (Sec. 4
                                 box) on the CPU, with iteration counts g.
+
+A lattice description with ``Lz`` > 1 is a 3D simple-cubic lattice (six
+neighbours, 14 classes, blocks bx x by x bz; ``sr_oracle3d.c``): ``des`` and
+``sr`` dispatch on it, and ``rate_table3`` gives its 14 class rates.
 """
 from __future__ import annotations
 
@@ -26,6 +30,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sr_oracle.c")
+_SRC3 = os.path.join(_HERE, "sr_oracle3d.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -38,7 +43,7 @@ STEP = {"continue": 0, "wipe": 1, 0: 0, 1: 1}
 def build() -> str:
     """Compile the oracle with gcc (always recompiles)."""
     cmd = ["gcc", "-std=c99", "-O2", "-Wall", "-fPIC", "-shared",
-           "-ffp-contract=off", "-o", _LIB, _SRC, "-lm"]
+           "-ffp-contract=off", "-o", _LIB, _SRC, _SRC3, "-lm"]
     subprocess.check_call(cmd)
     return _LIB
 
@@ -51,6 +56,16 @@ class _Params(C.Structure):
                 ("horizon_ticks", C.c_int64), ("burn_ticks", C.c_int64),
                 ("seed", C.c_uint64), ("init_spins", C.c_void_p),
                 ("step_rule", C.c_int32)]
+
+
+class _Params3(C.Structure):
+    _fields_ = [("Lx", C.c_int32), ("Ly", C.c_int32), ("Lz", C.c_int32),
+                ("bx", C.c_int32), ("by", C.c_int32), ("bz", C.c_int32),
+                ("J", C.c_double), ("h", C.c_double), ("T", C.c_double),
+                ("rule", C.c_int32), ("tick_bits", C.c_int32), ("init", C.c_int32),
+                ("window_ticks", C.c_int64), ("horizon_ticks", C.c_int64),
+                ("burn_ticks", C.c_int64), ("seed", C.c_uint64),
+                ("init_spins", C.c_void_p), ("step_rule", C.c_int32)]
 
 
 class _Result(C.Structure):
@@ -88,8 +103,21 @@ def lib():
         L.orc_des_run.argtypes = [C.POINTER(_Params), C.POINTER(_Result)]
         L.orc_sr_run.argtypes = [C.POINTER(_Params), C.POINTER(_Result),
                                  C.c_void_p, C.c_void_p, C.c_int32]
+        L.orc3_rate_table.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int,
+                                      C.POINTER(C.c_uint32)]
+        L.orc3_select_site.argtypes = [C.POINTER(_Params3), C.c_void_p, C.c_int,
+                                       C.c_uint64, C.POINTER(C.c_int64)]
+        L.orc3_subdomain_lambda.argtypes = [C.POINTER(_Params3), C.c_void_p, C.c_int,
+                                            C.POINTER(C.c_uint64)]
+        L.orc3_des_run.argtypes = [C.POINTER(_Params3), C.POINTER(_Result)]
+        L.orc3_sr_run.argtypes = [C.POINTER(_Params3), C.POINTER(_Result),
+                                  C.c_void_p, C.c_void_p, C.c_int32]
         _lib = L
     return _lib
+
+
+def is3d(p) -> bool:
+    return int(p.get("Lz", 1) or 1) > 1
 
 
 # ---------------------------------------------------------------- primitives
@@ -108,6 +136,15 @@ def expq(u: int, tick_bits: int = 28) -> int:
 def rate_table(J, h, T, rule="metropolis"):
     out = (C.c_uint32 * 10)()
     rc = lib().orc_rate_table(J, h, T, RULE[rule], out)
+    if rc != 0:
+        raise ValueError("bad rate-table parameters")
+    return np.array(list(out), dtype=np.uint32)
+
+
+def rate_table3(J, h, T, rule="metropolis"):
+    """The 14 class rates (Q28) of the 3D lattice, class 7*[s=-1] + n_up."""
+    out = (C.c_uint32 * 14)()
+    rc = lib().orc3_rate_table(J, h, T, RULE[rule], out)
     if rc != 0:
         raise ValueError("bad rate-table parameters")
     return np.array(list(out), dtype=np.uint32)
@@ -132,7 +169,11 @@ def to_ticks(x: float, tick_bits: int) -> int:
 def _cparams(p, burn=0.0, window=None):
     tb = int(p.get("tick_bits", 28))
     w = p["window"] if window is None else window
-    cp = _Params()
+    if is3d(p):
+        cp = _Params3()
+        cp.Lz, cp.bz = int(p["Lz"]), int(p["bz"])
+    else:
+        cp = _Params()
     cp.Lx, cp.Ly, cp.bx, cp.by = p["Lx"], p["Ly"], p["bx"], p["by"]
     cp.J, cp.h, cp.T = p["J"], p["h"], p["T"]
     cp.rule = RULE[p.get("rule", "metropolis")]
@@ -154,7 +195,8 @@ def select_site(p, spins, d, V):
     cp, _keep = _cparams(p)
     s = np.ascontiguousarray(spins, dtype=np.int8).reshape(-1)
     out = C.c_int64()
-    rc = lib().orc_select_site(C.byref(cp), s.ctypes.data, d, C.c_uint64(V), C.byref(out))
+    fn = lib().orc3_select_site if is3d(p) else lib().orc_select_site
+    rc = fn(C.byref(cp), s.ctypes.data, d, C.c_uint64(V), C.byref(out))
     if rc != 0:
         raise ValueError(f"select_site failed ({rc})")
     return int(out.value)
@@ -164,7 +206,8 @@ def subdomain_lambda(p, spins, d):
     cp, _keep = _cparams(p)
     s = np.ascontiguousarray(spins, dtype=np.int8).reshape(-1)
     out = C.c_uint64()
-    rc = lib().orc_subdomain_lambda(C.byref(cp), s.ctypes.data, d, C.byref(out))
+    fn = lib().orc3_subdomain_lambda if is3d(p) else lib().orc_subdomain_lambda
+    rc = fn(C.byref(cp), s.ctypes.data, d, C.byref(out))
     if rc != 0:
         raise ValueError("subdomain_lambda failed")
     return int(out.value)
@@ -173,12 +216,15 @@ def subdomain_lambda(p, spins, d):
 # ---------------------------------------------------------------- full runs
 def _run(p, kind, log=True, burn=0.0, log_cap=None, max_iters=0):
     cp, keep = _cparams(p, burn=burn)
-    nsub = (p["Lx"] // p["bx"]) * (p["Ly"] // p["by"])
+    three = is3d(p)
+    Lz = int(p["Lz"]) if three else 1
+    nsub = (p["Lx"] // p["bx"]) * (p["Ly"] // p["by"]) * (Lz // int(p["bz"]) if three else 1)
+    nsite = p["Lx"] * p["Ly"] * Lz
     nwin = 0 if cp.horizon_ticks == 0 else -(-cp.horizon_ticks // cp.window_ticks)
     if log_cap is None:
-        log_cap = int(1.25 * p["Lx"] * p["Ly"] * p["horizon"]) + 4096 if log else 0
+        log_cap = int(1.25 * nsite * p["horizon"]) + 4096 if log else 0
     while True:
-        spins = np.zeros(p["Lx"] * p["Ly"], dtype=np.int8)
+        spins = np.zeros(nsite, dtype=np.int8)
         lt = np.zeros(max(log_cap, 1), dtype=np.int64)
         ls = np.zeros(max(log_cap, 1), dtype=np.int64)
         lsub = np.zeros(max(log_cap, 1), dtype=np.int32)
@@ -197,17 +243,19 @@ def _run(p, kind, log=True, burn=0.0, log_cap=None, max_iters=0):
         r.snap_M, r.snap_bond = sM.ctypes.data, sB.ctypes.data
         r.carry = carry.ctypes.data
         if kind == "des":
-            rc = lib().orc_des_run(C.byref(cp), C.byref(r))
+            fn = lib().orc3_des_run if three else lib().orc_des_run
+            rc = fn(C.byref(cp), C.byref(r))
         else:
-            rc = lib().orc_sr_run(C.byref(cp), C.byref(r), g.ctypes.data,
-                                  f.ctypes.data, max_iters)
+            fn = lib().orc3_sr_run if three else lib().orc_sr_run
+            rc = fn(C.byref(cp), C.byref(r), g.ctypes.data, f.ctypes.data, max_iters)
         if rc != 0:
             raise RuntimeError(f"oracle {kind} failed with code {rc}")
         if not log or r.n_events <= log_cap:
             break
         log_cap = int(r.n_events)
     n = int(r.n_events)
-    out = dict(spins=spins.reshape(p["Ly"], p["Lx"]), n_events=n,
+    shape = (Lz, p["Ly"], p["Lx"]) if three else (p["Ly"], p["Lx"])
+    out = dict(spins=spins.reshape(shape), n_events=n,
                sub_flips=flips, sub_digest=dig, snap_M=sM, snap_bond=sB,
                carry=carry.reshape(nsub, 4), M=int(r.M), bond=int(r.bond),
                int_M=r.int_M, int_M2=r.int_M2, int_absM=r.int_absM,

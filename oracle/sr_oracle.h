@@ -47,6 +47,18 @@ typedef struct {
   int64_t int_ticks;
 } orc_result;
 
+/* 3D simple-cubic lattice (sr_oracle3d.c): 14 classes, six faces. */
+typedef struct {
+  int32_t Lx, Ly, Lz;      /* periodic lattice, each >= 2 */
+  int32_t bx, by, bz;      /* subdomain block, dividing the lattice */
+  double J, h, T;
+  int32_t rule, tick_bits, init;
+  int64_t window_ticks, horizon_ticks, burn_ticks;
+  uint64_t seed;
+  const int8_t* init_spins;/* Lz*Ly*Lx, for ORC_INIT_USER */
+  int32_t step_rule;
+} orc3_params;
+
 void orc_philox4x32_10(const uint32_t key[2], const uint32_t ctr[4], uint32_t out[4]);
 uint64_t orc_expq(uint64_t u, int tick_bits);
 int orc_rate_table(double J, double h, double T, int rule, uint32_t out[10]);
@@ -56,5 +68,11 @@ int orc_select_site(const orc_params* p, const int8_t* spins, int d, uint64_t V,
 int orc_subdomain_lambda(const orc_params* p, const int8_t* spins, int d, uint64_t* lam_out);
 int orc_des_run(const orc_params* p, orc_result* r);
 int orc_sr_run(const orc_params* p, orc_result* r, int32_t* g_out, int32_t* f_out, int32_t max_iters);
+
+int orc3_rate_table(double J, double h, double T, int rule, uint32_t out[14]);
+int orc3_select_site(const orc3_params* p, const int8_t* spins, int d, uint64_t V, int64_t* site_out);
+int orc3_subdomain_lambda(const orc3_params* p, const int8_t* spins, int d, uint64_t* lam_out);
+int orc3_des_run(const orc3_params* p, orc_result* r);
+int orc3_sr_run(const orc3_params* p, orc_result* r, int32_t* g_out, int32_t* f_out, int32_t max_iters);
 
 #endif
