@@ -99,6 +99,18 @@ typedef struct {
   int32_t step_rule;         /* SR_STEP_CONTINUE (0) or SR_STEP_WIPE: Sec. 5,
                                 "Subsequent steps" vs "An alternate approach
                                 to subsequent steps" (see below) */
+  int32_t Lz, bz;            /* 3D simple-cubic lattice (more dimensions and
+                                neighbours, Secs. 3 and 5) when Lz >= 4: six
+                                neighbours, 14 classes k = 7*[s = -1] + n_up,
+                                blocks bx x by x bz with 2 <= each side and
+                                every face (bx*by, by*bz, bx*bz) <= 64 sites,
+                                bz = 0: chosen by the tuner (cubic block).
+                                Lz = 0 or 1: the 2D square lattice (bz
+                                ignored).  Global site (z*Ly + y)*Lx + x;
+                                subdomain (cz*nby + cy)*nbx + cx.  3D runs
+                                take the plain path (not sr_batch_* or the
+                                server) and start every relaxation run at the
+                                window start */
 } sr_params;
 
 typedef struct {
@@ -125,6 +137,7 @@ typedef struct {
                                 simulation's stream), milliseconds */
   int64_t subdomain_runs;    /* subdomain-iterations actually simulated (the
                                 others kept their previous outputs) */
+  int32_t Lz, bz;            /* 3D lattice and block depth (0, 0 in 2D) */
 } sr_obs;
 
 typedef struct sr_sim sr_sim;
@@ -156,7 +169,8 @@ int sr_reset(sr_sim* s);
 /* Release everything.  NULL-safe. */
 void sr_destroy(sr_sim* s);
 
-/* Committed spins, Ly*Lx int8 row-major, into a caller-owned host buffer. */
+/* Committed spins, Ly*Lx int8 row-major (3D: Lz*Ly*Lx), into a
+ * caller-owned host buffer. */
 int sr_get_spins(sr_sim* s, int8_t* host_out);
 
 /* SR_LOG_FULL only: committed events of subdomain d (row-major block id) in
@@ -174,15 +188,18 @@ int sr_get_digests(sr_sim* s, uint64_t* digests, int64_t* flips);
  * hazard since then.  Caller-owned, 3 * n_sub int64. */
 int sr_get_carry(sr_sim* s, int64_t* out);
 
-/* The 10 class rates round(2^28 p_k), class k = 5*[s = -1] + (up neighbours). */
-int sr_get_rate_table(sr_sim* s, uint32_t out[10]);
+/* The class rates round(2^28 p_k): 10 on the square lattice, class
+ * k = 5*[s = -1] + (up neighbours); 14 on the simple-cubic one,
+ * k = 7*[s = -1] + (up neighbours).  out must hold 14 entries; the first 10
+ * or 14 are written. */
+int sr_get_rate_table(sr_sim* s, uint32_t out[14]);
 
 /* The same table computed from parameters alone, as sr_create computes it
  * (eqs. hamil, pMin / pglauber in IEEE double on the host; no device work,
  * so it may be called without a GPU).  Reads J, h, T and rule only.
  * SR_EINVAL for a null argument, T <= 0, non-finite J, h or T, or an unknown
  * rule. */
-int sr_rate_table(const sr_params* p, uint32_t out[10]);
+int sr_rate_table(const sr_params* p, uint32_t out[14]);
 
 /* Checkpoint of the committed state (committed time is a consistent cut,
  * Sec. 4): committed spins, per-subdomain carry, counters, and for an
@@ -237,7 +254,8 @@ int sr_batch_step_static(sr_sim* const* sims, int32_t n, int32_t max_windows, vo
  * 0 or window = 0).  Block: a fixed table over (L, T) -- never load-dependent,
  * because the block partition keys the random streams and so the trajectory.
  * First window: 4 x the step-size rule T_max = log N / (lambda |dG_i|) of
- * Sec. 5, clamped to [1/8, 2].  A simulation created with window = 0 then
+ * Sec. 5, clamped to [1/8, 2].  A 3D lattice (Lz >= 4) gets a cubic block
+ * (bz = bx), 8^3 halved until it divides every side.  A simulation created with window = 0 then
  * adapts its step size after every committed window from the measured
  * iterations g (Sec. 4 box: a step size is chosen at each step), aiming at
  * about 16 iterations per window; the trajectory does not depend on it. */

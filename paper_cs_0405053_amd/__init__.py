@@ -51,7 +51,8 @@ class Params(C.Structure):
                 ("window", C.c_double), ("horizon", C.c_double), ("seed", C.c_uint64),
                 ("init", C.c_int32), ("init_spins", C.c_void_p), ("log_mode", C.c_int32),
                 ("max_iters", C.c_int32), ("tick_bits", C.c_int32), ("hist_cap", C.c_int32),
-                ("wlog_cap", C.c_int32), ("step_rule", C.c_int32)]
+                ("wlog_cap", C.c_int32), ("step_rule", C.c_int32), ("Lz", C.c_int32),
+                ("bz", C.c_int32)]
 
 
 class Obs(C.Structure):
@@ -62,7 +63,7 @@ class Obs(C.Structure):
                 ("by", C.c_int32), ("Lx", C.c_int32), ("Ly", C.c_int32),
                 ("window_ticks", C.c_int64), ("horizon_ticks", C.c_int64),
                 ("relax_launches", C.c_int64), ("relax_ms", C.c_double),
-                ("subdomain_runs", C.c_int64)]
+                ("subdomain_runs", C.c_int64), ("Lz", C.c_int32), ("bz", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -153,8 +154,9 @@ def to_params(p: Dict) -> (Params, Optional[np.ndarray]):
     keep = None
     if cp.init == 2 and p.get("init_spins") is not None:
         keep = np.ascontiguousarray(p["init_spins"], dtype=np.int8).reshape(-1)
-        if keep.size != cp.Lx * cp.Ly:
-            raise SRError(SR_EINVAL, "init_spins must hold Lx*Ly values")
+        nz = int(p.get("Lz", 0) or 0)
+        if keep.size != cp.Lx * cp.Ly * max(nz, 1):
+            raise SRError(SR_EINVAL, "init_spins must hold Lx*Ly (3D: Lx*Ly*Lz) values")
         cp.init_spins = keep.ctypes.data
     cp.log_mode = _LOG[p.get("log_mode", "digest")]
     cp.max_iters = int(p.get("max_iters", 0))
@@ -162,6 +164,8 @@ def to_params(p: Dict) -> (Params, Optional[np.ndarray]):
     cp.hist_cap = int(p.get("hist_cap", 0))
     cp.wlog_cap = int(p.get("wlog_cap", 0))
     cp.step_rule = _STEP[p.get("step", "continue")]
+    cp.Lz = int(p.get("Lz", 0) or 0)
+    cp.bz = int(p.get("bz", 0) or 0)
     return cp, keep
 
 
@@ -181,14 +185,14 @@ def tune(p: Dict):
 
 
 def rate_table(p: Dict) -> np.ndarray:
-    """The 10 class rates the library computes for these parameters (host
-    only, no device work)."""
+    """The class rates the library computes for these parameters (host only,
+    no device work): 10 in 2D, 14 for a 3D lattice (Lz > 1)."""
     cp, _ = to_params(p)
-    r = np.zeros(10, dtype=np.uint32)
+    r = np.zeros(14, dtype=np.uint32)
     rc = lib().sr_rate_table(C.byref(cp), r.ctypes.data)
     if rc != SR_OK:
         raise SRError(rc, "sr_rate_table rejected the parameters")
-    return r
+    return r[:14 if cp.Lz > 1 else 10].copy()
 
 
 class Sim:
@@ -267,9 +271,10 @@ class Sim:
 
     def spins(self) -> np.ndarray:
         o = self.observables()
-        buf = np.zeros(o["Ly"] * o["Lx"], dtype=np.int8)
+        nz = o["Lz"] if o["Lz"] > 1 else 1
+        buf = np.zeros(nz * o["Ly"] * o["Lx"], dtype=np.int8)
         self._check(lib().sr_get_spins(self._h, buf.ctypes.data), "sr_get_spins")
-        return buf.reshape(o["Ly"], o["Lx"])
+        return buf.reshape(nz, o["Ly"], o["Lx"]) if o["Lz"] > 1 else buf.reshape(o["Ly"], o["Lx"])
 
     def log(self, d: int):
         n = C.c_int64()
@@ -295,9 +300,9 @@ class Sim:
         return c.reshape(n, 3)
 
     def rate_table(self) -> np.ndarray:
-        r = np.zeros(10, dtype=np.uint32)
+        r = np.zeros(14, dtype=np.uint32)
         self._check(lib().sr_get_rate_table(self._h, r.ctypes.data), "sr_get_rate_table")
-        return r
+        return r[:14 if self.observables()["Lz"] > 1 else 10].copy()
 
     def save(self) -> bytes:
         n = C.c_size_t()

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsr.so")
-SOURCES = ["sr_kernels.hip", "sr_api.hip"]
+SOURCES = ["sr_kernels.hip", "sr_kernels3d.hip", "sr_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

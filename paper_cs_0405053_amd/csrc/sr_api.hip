@@ -31,10 +31,12 @@ hipError_t launch_init_random(int8_t* s, int64_t n, uint64_t seed, hipStream_t s
 hipError_t launch_fill(int8_t* s, int64_t n, int8_t v, hipStream_t stream);
 hipError_t launch_observables(const int8_t* s, int Lx, int Ly, unsigned long long* out,
                               hipStream_t stream);
-hipError_t launch_batch(const BatchArgs& B, int waves, size_t lds, hipStream_t stream);
+hipError_t launch_observables3d(const int8_t* s, int Lx, int Ly, int Lz, unsigned long long* out,
+                                hipStream_t stream);
+hipError_t launch_batch(const BatchArgs& B, int shape, int waves, size_t lds, hipStream_t stream);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t stream);
 hipError_t build_window_graph(const Lattice& L, const Step* dstep, int k, hipGraphExec_t* out);
-int batch_waves_per_cu(size_t lds);
+int batch_waves_per_cu(int shape, size_t lds);
 size_t relax_lds(const Lattice& L);
 }  // namespace sr
 
@@ -95,14 +97,17 @@ static int64_t to_ticks(double x, int tick_bits) {
   return (int64_t)std::llround(std::ldexp(x, tick_bits));
 }
 
-// Class rates round(2^28 p_k), k = 5*[s=-1] + n_up; p from eq. pMin or
-// eq. pglauber with dE = 2 s (J (2 n_up - 4) + h) (eq. hamil, each bond once).
-static int rate_table(double J, double h, double T, int rule, uint32_t out[kClasses]) {
+// Class rates round(2^28 p_k), k = (z+1)*[s=-1] + n_up for z neighbours (z = 4
+// on the square lattice, 10 classes; z = 6 on the simple-cubic one, 14); p
+// from eq. pMin or eq. pglauber with dE = 2 s (J (2 n_up - z) + h) (eq.
+// hamil, each bond once).
+static int rate_table(double J, double h, double T, int rule, int z, uint32_t out[kMaxClasses]) {
   if (!(T > 0.0) || (rule != SR_METROPOLIS && rule != SR_GLAUBER)) return -1;
-  for (int k = 0; k < kClasses; ++k) {
-    int s = (k < 5) ? 1 : -1;
-    int nup = k % 5;
-    double x = -(2.0 * s * (J * (2 * nup - 4) + h)) / T;
+  const int ncls = 2 * (z + 1);
+  for (int k = 0; k < ncls; ++k) {
+    int s = (k <= z) ? 1 : -1;
+    int nup = k % (z + 1);
+    double x = -(2.0 * s * (J * (2 * nup - z) + h)) / T;
     double p;
     if (rule == SR_METROPOLIS) {
       double theta = std::exp(x);
@@ -121,7 +126,7 @@ extern "C" int sr_rate_table(const sr_params* p, uint32_t out[10]) {
   if (!p || !out) return SR_EINVAL;
   if (!(p->T > 0.0) || !std::isfinite(p->T) || !std::isfinite(p->J) || !std::isfinite(p->h))
     return SR_EINVAL;
-  return rate_table(p->J, p->h, p->T, p->rule, out) == 0 ? SR_OK : SR_EINVAL;
+  return rate_table(p->J, p->h, p->T, p->rule, p->Lz > 1 ? 6 : 4, out) == 0 ? SR_OK : SR_EINVAL;
 }
 
 static int sites_per_lane_shift(int nblk) {
@@ -136,6 +141,20 @@ static const char* check_block(int Lx, int Ly, int bx, int by) {
   if (Lx % bx || Ly % by) return "Lx % bx and Ly % by must be 0";
   return nullptr;
 }
+
+// 3D blocks: every face holds at most 64 sites (a halo face is one 64-bit
+// mask per wave) and the block at most 1024.
+static const char* check_block3(int Lx, int Ly, int Lz, int bx, int by, int bz) {
+  if (bx < 2 || by < 2 || bz < 2) return "bx, by and bz must be >= 2";
+  if (bx * by > 64 || by * bz > 64 || bx * bz > 64) return "every face of a 3D block must hold <= 64 sites";
+  if (Lx % bx || Ly % by || Lz % bz) return "Lx % bx, Ly % by and Lz % bz must be 0";
+  return nullptr;
+}
+
+static bool is3d(const sr_params& p) { return p.Lz > 1; }
+static int faces_of(const Lattice& L) { return L.Lz > 1 ? kFaces3 : kEdges; }
+static size_t sites_of(const Lattice& L) { return (size_t)L.Lx * L.Ly * L.Lz; }
+static int classes_of(const Lattice& L) { return L.Lz > 1 ? kClasses3 : kClasses; }
 
 // The wipe rule makes the trajectory depend on the window, so it needs a
 // window fixed by the caller (a tuned one adapts to measured iterations).
@@ -153,6 +172,23 @@ static const char* check_step_rule(int rule, bool tuned_window) {
 // does not change results, only iteration counts.
 extern "C" int sr_tune(const sr_params* p, int32_t* bx, int32_t* by, double* window) {
   if (!p || p->Lx < 4 || p->Ly < 4) return SR_EINVAL;
+  if (p->Lz > 1) {
+    // 3D: a cubic block, 8^3 (64-site faces) halved until it divides the
+    // lattice; |dG| = b^3 - (b-2)^3 surface sites
+    if (p->Lz < 4) return SR_EINVAL;
+    int b = 8;
+    while (b > 2 && (p->Lx % b || p->Ly % b || p->Lz % b)) b >>= 1;
+    if (check_block3(p->Lx, p->Ly, p->Lz, b, b, b)) return SR_EINVAL;
+    if (bx) *bx = b;
+    if (by) *by = b;
+    if (window) {
+      double nsub = (double)(p->Lx / b) * (double)(p->Ly / b) * (double)(p->Lz / b);
+      double dG = (double)(b * b * b - (b - 2) * (b - 2) * (b - 2));
+      double tmax = std::log(std::max(nsub, 2.0)) / dG;
+      *window = std::min(std::max(4.0 * tmax, 0.125), 2.0);
+    }
+    return SR_OK;
+  }
   int b = 16;
   int minL = std::min(p->Lx, p->Ly);
   if (minL >= 2048 && p->T <= 1.25) b = 32;   // sparse flips: amortise per-window cost
@@ -186,7 +222,7 @@ static void free_hist(sr_sim* s) {
 
 static int alloc_hist(sr_sim* s) {
   Lattice& L = s->L;
-  size_t nh = 2 * (size_t)L.nsub * kEdges * (size_t)L.hcap;
+  size_t nh = 2 * (size_t)L.nsub * faces_of(L) * (size_t)L.hcap;
   if (hipMalloc(&L.hist, nh * sizeof(uint64_t)) != hipSuccess)
     SR_FAIL(s, SR_ENOMEM, "cannot allocate %zu boundary-list entries", nh);
   if (hipMalloc(&L.wlog, (size_t)L.nsub * L.wcap * sizeof(uint64_t)) != hipSuccess)
@@ -246,19 +282,23 @@ struct Plan {
 constexpr int kCkIntPlain = 4, kCkIntBatch = 8;
 static Plan plan(const sr_params& p, int64_t Wmax) {
   Plan pl;
+  const bool d3 = is3d(p);
+  const int bz = d3 ? p.bz : 1, Lz = d3 ? p.Lz : 1, nf = d3 ? kFaces3 : kEdges;
   double wt = std::ldexp((double)Wmax, -p.tick_bits);
-  double edge = std::max(p.bx, p.by) * wt, blk = (double)p.bx * p.by * wt;
-  pl.hcap = (int)std::min((double)kMaxHistCap,
+  double face = d3 ? (double)std::max(p.bx * p.by, std::max(p.by * bz, p.bx * bz)) : (double)std::max(p.bx, p.by);
+  double edge = face * wt, blk = (double)p.bx * p.by * bz * wt;
+  pl.hcap = (int)std::min((double)(d3 ? kMaxHistCap3 : kMaxHistCap),
                           std::max(32.0, std::ceil((edge + 6.0 * std::sqrt(edge)) / 32.0) * 32.0));
   pl.wcap = (int)std::max(64.0, std::ceil((blk + 6.0 * std::sqrt(blk) + 32.0) / 64.0) * 64.0);
   if (p.hist_cap > 0) pl.hcap = p.hist_cap;
   if (p.wlog_cap > 0) pl.wcap = p.wlog_cap;
   pl.ckint = kCkIntPlain;
-  pl.nck = (int)std::min(32.0, std::max(4.0, std::ceil(1.5 * blk / pl.ckint) + 1.0));
-  size_t nsub = (size_t)(p.Lx / p.bx) * (p.Ly / p.by), nsite = (size_t)p.Lx * p.Ly;
-  pl.bytes = 2 * nsite + 2 * nsub * sizeof(Carry) + 2 * nsub * kEdges * (sizeof(uint32_t) + sizeof(int64_t)) +
+  // (3D runs always start at the window start: one unused checkpoint slot)
+  pl.nck = d3 ? 1 : (int)std::min(32.0, std::max(4.0, std::ceil(1.5 * blk / pl.ckint) + 1.0));
+  size_t nsub = (size_t)(p.Lx / p.bx) * (p.Ly / p.by) * (Lz / bz), nsite = (size_t)p.Lx * p.Ly * Lz;
+  pl.bytes = 2 * nsite + 2 * nsub * sizeof(Carry) + 2 * nsub * nf * (sizeof(uint32_t) + sizeof(int64_t)) +
              4 * (size_t)need_stride((int)nsub) + nsub * pl.nck * sizeof(Ckpt) + 2 * nsub * sizeof(uint32_t) +
-             2 * nsub * kEdges * (size_t)pl.hcap * sizeof(uint64_t) + nsub * (size_t)pl.wcap * sizeof(uint64_t) +
+             2 * nsub * nf * (size_t)pl.hcap * sizeof(uint64_t) + nsub * (size_t)pl.wcap * sizeof(uint64_t) +
              2 * (size_t)need_stride((int)nsub) + nsub * sizeof(SubStat) + (p.init == SR_INIT_USER ? nsite : 0) +
              64 * 1024;
   return pl;
@@ -270,13 +310,17 @@ static int resolve(sr_params& p, bool& tuned_window, std::string& why) {
   if (p.tick_bits == 0) p.tick_bits = 28;
   if (p.tick_bits < 4 || p.tick_bits > 28) { why = "tick_bits must be in [4, 28]"; return SR_EINVAL; }
   tuned_window = (p.window == 0.0);
-  if (p.bx == 0 || p.by == 0 || p.window == 0.0) {
+  if (p.Lz < 0 || p.Lz == 2 || p.Lz == 3) { why = "Lz must be 0 or 1 (2D) or >= 4 (3D)"; return SR_EINVAL; }
+  if (p.bx == 0 || p.by == 0 || (is3d(p) && p.bz == 0) || p.window == 0.0) {
     int32_t tbx, tby; double tw;
     if (sr_tune(&p, &tbx, &tby, &tw) != SR_OK) { why = "tuner found no block"; return SR_EINVAL; }
-    if (p.bx == 0 || p.by == 0) { p.bx = tbx; p.by = tby; }
+    if (p.bx == 0 || p.by == 0 || (is3d(p) && p.bz == 0)) { p.bx = tbx; p.by = tby; if (is3d(p)) p.bz = tbx; }
     if (p.window == 0.0) p.window = tw;
   }
-  if (const char* w = check_block(p.Lx, p.Ly, p.bx, p.by)) { why = w; return SR_EINVAL; }
+  if (const char* w = is3d(p) ? check_block3(p.Lx, p.Ly, p.Lz, p.bx, p.by, p.bz) : check_block(p.Lx, p.Ly, p.bx, p.by)) {
+    why = w;
+    return SR_EINVAL;
+  }
   if (!(p.window > 0.0) || !std::isfinite(p.window)) { why = "window must be > 0"; return SR_EINVAL; }
   if (const char* w = check_step_rule(p.step_rule, tuned_window)) { why = w; return SR_EINVAL; }
   return SR_OK;
@@ -300,21 +344,24 @@ static int create_impl(const sr_params* pin, void* stream, sr_sim** out, bool in
     SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "unknown init mode");
   const bool tuned_window = (p.window == 0.0);
   if (const char* why = check_step_rule(p.step_rule, tuned_window)) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "%s", why);
-  if (p.bx == 0 || p.by == 0 || p.window == 0.0) {
+  if (p.Lz < 0 || p.Lz == 2 || p.Lz == 3) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "Lz must be 0 or 1 (2D) or >= 4 (3D)");
+  if (p.bx == 0 || p.by == 0 || (is3d(p) && p.bz == 0) || p.window == 0.0) {
     int32_t tbx, tby; double tw;
     if (sr_tune(&p, &tbx, &tby, &tw) != SR_OK) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "tuner found no block");
-    if (p.bx == 0 || p.by == 0) { p.bx = tbx; p.by = tby; }
+    if (p.bx == 0 || p.by == 0 || (is3d(p) && p.bz == 0)) { p.bx = tbx; p.by = tby; if (is3d(p)) p.bz = tbx; }
     if (p.window == 0.0) p.window = tw;
   }
-  if (const char* why = check_block(p.Lx, p.Ly, p.bx, p.by)) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "%s", why);
+  if (const char* why = is3d(p) ? check_block3(p.Lx, p.Ly, p.Lz, p.bx, p.by, p.bz) : check_block(p.Lx, p.Ly, p.bx, p.by))
+    SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "%s", why);
+  if (!is3d(p)) { p.Lz = 0; p.bz = 0; }
   if (!(p.window > 0.0) || !std::isfinite(p.window)) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "window must be > 0");
   int64_t W = to_ticks(p.window, p.tick_bits), H = to_ticks(p.horizon, p.tick_bits);
   if (W < 1) W = 1;
   if (H >= ((int64_t)1 << 46)) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "horizon too long for the tick grid");
   if (p.max_iters <= 0) p.max_iters = 10000;
   if (p.hist_cap < 0 || p.wlog_cap < 0) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "capacities must be >= 0");
-  if (p.hist_cap > kMaxHistCap)   // a relaxation wave keeps 12 lists of this length in LDS
-    SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "hist_cap must be <= %d", kMaxHistCap);
+  if (p.hist_cap > (is3d(p) ? kMaxHistCap3 : kMaxHistCap))   // a wave keeps 12 (3D: 18) lists of this length in LDS
+    SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "hist_cap must be <= %d", is3d(p) ? kMaxHistCap3 : kMaxHistCap);
 
   sr_sim* s = new sr_sim();
   s->p = p;
@@ -327,12 +374,13 @@ static int create_impl(const sr_params* pin, void* stream, sr_sim** out, bool in
   Lattice& L = s->L;
   std::memset(&L, 0, sizeof(L));
   L.Lx = p.Lx; L.Ly = p.Ly; L.bx = p.bx; L.by = p.by;
-  L.nbx = p.Lx / p.bx; L.nby = p.Ly / p.by; L.nsub = L.nbx * L.nby;
-  L.sshift = sites_per_lane_shift(p.bx * p.by);
+  L.Lz = is3d(p) ? p.Lz : 1; L.bz = is3d(p) ? p.bz : 1;
+  L.nbx = p.Lx / p.bx; L.nby = p.Ly / p.by; L.nbz = L.Lz / L.bz; L.nsub = L.nbx * L.nby * L.nbz;
+  L.sshift = sites_per_lane_shift(p.bx * p.by * L.bz);
   L.S = 1 << L.sshift;
   L.tick_bits = p.tick_bits;
   L.wipe = p.step_rule == SR_STEP_WIPE ? 1 : 0;
-  if (rate_table(p.J, p.h, p.T, p.rule, L.rate) != 0) { delete s; SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "bad rate parameters"); }
+  if (rate_table(p.J, p.h, p.T, p.rule, is3d(p) ? 6 : 4, L.rate) != 0) { delete s; SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "bad rate parameters"); }
   L.seed_lo = (uint32_t)p.seed; L.seed_hi = (uint32_t)(p.seed >> 32);
   if (s->tune) s->Wmax = std::max(s->Wmin, std::min(s->Wmax, 4 * W));
   const Plan pl = plan(p, s->tune ? s->Wmax : W);
@@ -341,7 +389,7 @@ static int create_impl(const sr_params* pin, void* stream, sr_sim** out, bool in
   L.ckint = pl.ckint;
   L.nck = pl.nck;
 
-  size_t nsite = (size_t)p.Lx * p.Ly;
+  size_t nsite = sites_of(L);
   auto fail = [&](int code, const char* what) {
     g_create_err = what;
     free_all(s);
@@ -350,10 +398,10 @@ static int create_impl(const sr_params* pin, void* stream, sr_sim** out, bool in
   };
   if (hipMalloc(&L.spins, 2 * nsite) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate lattice");
   if (hipMalloc(&L.carry, 2 * (size_t)L.nsub * sizeof(Carry)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate carry");
-  if (hipMalloc(&L.hcnt, 2 * (size_t)L.nsub * kEdges * sizeof(uint32_t)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate list counts");
+  if (hipMalloc(&L.hcnt, 2 * (size_t)L.nsub * faces_of(L) * sizeof(uint32_t)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate list counts");
   if (hipMalloc(&L.slot, 2 * (size_t)need_stride(L.nsub)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate slots");
   if (hipMalloc(&L.chg, 2 * (size_t)need_stride(L.nsub)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate change flags");
-  if (hipMalloc(&L.fct, 2 * (size_t)L.nsub * kEdges * sizeof(int64_t)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate change ticks");
+  if (hipMalloc(&L.fct, 2 * (size_t)L.nsub * faces_of(L) * sizeof(int64_t)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate change ticks");
   if (hipMalloc(&L.ck, (size_t)L.nsub * L.nck * sizeof(Ckpt)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate checkpoints");
   if (hipMalloc(&L.ckn, (size_t)L.nsub * sizeof(uint32_t)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate checkpoint counts");
   if (hipMalloc(&L.stat, (size_t)L.nsub * sizeof(SubStat)) != hipSuccess) return fail(SR_ENOMEM, "cannot allocate work counters");
@@ -422,8 +470,9 @@ extern "C" const char* sr_last_error(const sr_sim* s) {
 static int grow(sr_sim* s, uint32_t ovf) {
   Lattice& L = s->L;
   if (ovf & 1u) {
-    if (L.hcap >= kMaxHistCap) SR_FAIL(s, SR_EOVERFLOW, "boundary list capacity limit reached");
-    L.hcap = std::min(2 * L.hcap, kMaxHistCap);
+    const int cap = L.Lz > 1 ? kMaxHistCap3 : kMaxHistCap;
+    if (L.hcap >= cap) SR_FAIL(s, SR_EOVERFLOW, "boundary list capacity limit reached");
+    L.hcap = std::min(2 * L.hcap, cap);
   }
   if (ovf & 2u) {
     if (L.wcap >= (1 << 22)) SR_FAIL(s, SR_EOVERFLOW, "window log capacity limit reached");
@@ -442,13 +491,13 @@ static int commit(sr_sim* s) {
     HIP_OR_FAIL(s, hipMemcpyAsync(wl.data(), L.wlog, wl.size() * 8, hipMemcpyDeviceToHost, s->stream));
     HIP_OR_FAIL(s, hipStreamSynchronize(s->stream));
     for (int d = 0; d < L.nsub; ++d) {
-      int x0 = (d % L.nbx) * L.bx, y0 = (d / L.nbx) * L.by;
+      const int x0 = (d % L.nbx) * L.bx, y0 = ((d / L.nbx) % L.nby) * L.by, z0 = (d / (L.nbx * L.nby)) * L.bz;
       for (uint32_t i = 0; i < cnt[d]; ++i) {
         uint64_t e = wl[(size_t)d * L.wcap + i];
         int v = (int)(e & 0xFFFF);
-        int ly = v / L.bx, lx = v % L.bx;
+        int lx = v % L.bx, t = v / L.bx, ly = t % L.by, lz = t / L.by;
         s->log_tick[d].push_back((int64_t)(e >> kPosBits));
-        s->log_site[d].push_back((int64_t)(y0 + ly) * L.Lx + x0 + lx);
+        s->log_site[d].push_back(((int64_t)(z0 + lz) * L.Ly + y0 + ly) * L.Lx + x0 + lx);
       }
     }
   }
@@ -561,7 +610,8 @@ extern "C" int sr_observables(sr_sim* s, sr_obs* o) {
   Lattice& L = s->L;
   unsigned long long h[2];
   HIP_OR_FAIL(s, hipMemsetAsync(s->obs, 0, 2 * sizeof(unsigned long long), s->stream));
-  HIP_OR_FAIL(s, launch_observables(spins_at(L, s->st.wp), L.Lx, L.Ly, s->obs, s->stream));
+  if (L.Lz > 1) HIP_OR_FAIL(s, launch_observables3d(spins_at(L, s->st.wp), L.Lx, L.Ly, L.Lz, s->obs, s->stream));
+  else HIP_OR_FAIL(s, launch_observables(spins_at(L, s->st.wp), L.Lx, L.Ly, s->obs, s->stream));
   HIP_OR_FAIL(s, hipMemcpyAsync(h, s->obs, sizeof(h), hipMemcpyDeviceToHost, s->stream));
   std::vector<Carry> c(L.nsub);
   std::vector<SubStat> w(L.nsub);
@@ -591,6 +641,7 @@ extern "C" int sr_observables(sr_sim* s, sr_obs* o) {
   o->n_sub = L.nsub;
   o->bx = L.bx; o->by = L.by;
   o->Lx = L.Lx; o->Ly = L.Ly;
+  o->Lz = L.Lz > 1 ? L.Lz : 0; o->bz = L.Lz > 1 ? L.bz : 0;
   o->window_ticks = s->W;
   o->horizon_ticks = s->H;
   o->relax_launches = s->relax_launches;
@@ -601,7 +652,7 @@ extern "C" int sr_observables(sr_sim* s, sr_obs* o) {
 extern "C" int sr_reset(sr_sim* s) {
   if (!s) return SR_EINVAL;
   Lattice& L = s->L;
-  int64_t nsite = (int64_t)L.Lx * L.Ly;
+  int64_t nsite = (int64_t)sites_of(L);
   if (s->p.init == SR_INIT_RANDOM) HIP_OR_FAIL(s, launch_init_random(spins_at(L, 0), nsite, s->p.seed, s->stream));
   else if (s->p.init == SR_INIT_ALL_UP) HIP_OR_FAIL(s, launch_fill(spins_at(L, 0), nsite, 1, s->stream));
   else if (s->init_copy) HIP_OR_FAIL(s, hipMemcpyAsync(spins_at(L, 0), s->init_copy, (size_t)nsite, hipMemcpyDeviceToDevice, s->stream));
@@ -622,7 +673,7 @@ extern "C" int sr_reset(sr_sim* s) {
 
 extern "C" int sr_get_spins(sr_sim* s, int8_t* out) {
   if (!s || !out) return SR_EINVAL;
-  HIP_OR_FAIL(s, hipMemcpyAsync(out, spins_at(s->L, s->st.wp), (size_t)s->L.Lx * s->L.Ly, hipMemcpyDeviceToHost, s->stream));
+  HIP_OR_FAIL(s, hipMemcpyAsync(out, spins_at(s->L, s->st.wp), sites_of(s->L), hipMemcpyDeviceToHost, s->stream));
   HIP_OR_FAIL(s, hipStreamSynchronize(s->stream));
   return SR_OK;
 }
@@ -675,7 +726,7 @@ extern "C" int sr_get_carry(sr_sim* s, int64_t* out) {
 
 extern "C" int sr_get_rate_table(sr_sim* s, uint32_t out[10]) {
   if (!s || !out) return SR_EINVAL;
-  std::memcpy(out, s->L.rate, sizeof(s->L.rate));
+  std::memcpy(out, s->L.rate, (size_t)classes_of(s->L) * sizeof(uint32_t));
   return SR_OK;
 }
 
@@ -696,7 +747,7 @@ struct SaveHeader {
 
 extern "C" int sr_save(sr_sim* s, void* blob, size_t cap, size_t* n) {
   if (!s || !n) return SR_EINVAL;
-  size_t nsite = (size_t)s->L.Lx * s->L.Ly;
+  size_t nsite = sites_of(s->L);
   const bool has_init = s->init_copy != nullptr;
   size_t need = sizeof(SaveHeader) + nsite + (size_t)s->L.nsub * sizeof(Carry) + (has_init ? nsite : 0);
   *n = need;
@@ -734,7 +785,7 @@ extern "C" int sr_load(const void* blob, size_t n, void* stream, sr_sim** out) {
   std::memcpy(&h, blob, sizeof(h));
   if (std::memcmp(h.magic, "SRCKPT3", 8) != 0) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "not a checkpoint");
   if (h.p.Lx < 4 || h.p.Ly < 4 || h.nsub <= 0) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "bad checkpoint header");
-  size_t nsite = (size_t)h.p.Lx * h.p.Ly;
+  size_t nsite = (size_t)h.p.Lx * h.p.Ly * (h.p.Lz > 1 ? h.p.Lz : 1);
   size_t need = sizeof(h) + nsite + (size_t)h.nsub * sizeof(Carry) + (h.has_init ? nsite : 0);
   if (n < need) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "truncated checkpoint");
   // a tuned simulation is re-created as tuned (the tuner is deterministic,
@@ -833,14 +884,17 @@ static int batch_core(sr_sim* const* sims, int32_t n, int32_t max_windows, hipSt
   int m = 0;
   size_t lds = 16;
   uint64_t total = 0;
+  bool all16 = true;   // every lattice 16x16 blocks without self-wrap
   for (int i = 0; i < n; ++i) {
     sr_sim* s = sims[i];
     if (!s) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "null simulation in batch");
     if (s->p.log_mode != SR_LOG_DIGEST) SR_FAIL(s, SR_EINVAL, "batched runs keep digests only (SR_LOG_DIGEST)");
     if (s->L.nsub >= (1 << 20)) SR_FAIL(s, SR_EINVAL, "too many subdomains for the batch queue");
+    if (s->L.Lz > 1) SR_FAIL(s, SR_EINVAL, "batched runs take 2D lattices only");
     if (s->st.t_c >= s->H) continue;
     if (m >= hs.cap) SR_FAIL(s, SR_EINVAL, "at most %d lattices per batch here", hs.cap);
     hs.idx[m++] = i;
+    all16 &= s->L.bx == 16 && s->L.by == 16 && s->L.nbx > 1 && s->L.nby > 1;
     lds = std::max(lds, relax_lds(s->L));
     total += (uint64_t)s->L.nsub;
   }
@@ -849,7 +903,16 @@ static int batch_core(sr_sim* const* sims, int32_t n, int32_t max_windows, hipSt
   int dev_id = 0, ncu = 0;
   HIP_OR_FAIL(s0, hipGetDevice(&dev_id));
   HIP_OR_FAIL(s0, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev_id));
-  int per_cu = batch_waves_per_cu(lds);
+  // the compile-time 16x16 body pays off on large lattices (measured: three
+  // 1024x1024 lattices 5.8e7 -> 6.3e7 flips/s); on many small ones the
+  // runtime-shape kernel with more waves per SIMD is faster (512 lattices of
+  // 32..512: 8.3e7 vs 8.1e7)
+  int shape = (all16 && total >= 1024 * (uint64_t)m) ? kBatch16NoWrap : kBatchGeneric;
+  if (const char* k = std::getenv("SR_BATCH_KERNEL")) {     // test knob: force one kernel
+    if (!std::strcmp(k, "generic")) shape = kBatchGeneric;
+    else if (!std::strcmp(k, "16x16") && all16) shape = kBatch16NoWrap;
+  }
+  int per_cu = batch_waves_per_cu(shape, lds);
   if (per_cu <= 0) SR_FAIL(s0, SR_EDEVICE, "cannot size the persistent grid");
   int waves = std::max(per_cu * ncu, kShards);   // every shard needs a wave
   // a shard's ring holds its share of every lattice's current iteration
@@ -905,7 +968,7 @@ static int batch_core(sr_sim* const* sims, int32_t n, int32_t max_windows, hipSt
   if (launch_zero(base + bl.rem, bl.total - bl.rem, stream) != hipSuccess ||
       hipMemcpyAsync(dlat, hs.lat, m * sizeof(Lattice), hipMemcpyHostToDevice, stream) != hipSuccess ||
       hipMemcpyAsync(drun, hs.run, m * sizeof(LatRun), hipMemcpyHostToDevice, stream) != hipSuccess ||
-      hipEventRecord(e0, stream) != hipSuccess || launch_batch(args, waves, lds, stream) != hipSuccess ||
+      hipEventRecord(e0, stream) != hipSuccess || launch_batch(args, shape, waves, lds, stream) != hipSuccess ||
       hipEventRecord(e1, stream) != hipSuccess ||
       hipMemcpyAsync(hs.run, drun, m * sizeof(LatRun), hipMemcpyDeviceToHost, stream) != hipSuccess ||
       hipMemcpyAsync(&ctr, dctr, sizeof(ctr), hipMemcpyDeviceToHost, stream) != hipSuccess ||
@@ -1094,6 +1157,7 @@ extern "C" int sr_server_submit(sr_server* v, const sr_params* pin, uint64_t* re
   if (!v || !pin) return SR_EINVAL;
   sr_params p = *pin;
   if (p.log_mode != SR_LOG_DIGEST) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "served requests keep digests only");
+  if (p.Lz > 1) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "served requests are 2D lattices");
   bool tuned = false;
   std::string why;
   if (resolve(p, tuned, why) != SR_OK) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "%s", why.c_str());

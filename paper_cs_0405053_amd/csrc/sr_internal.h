@@ -7,6 +7,8 @@
 namespace sr {
 
 constexpr int kClasses = 10;             // Sec. 3: 2 spin states x 5 up-counts
+constexpr int kClasses3 = 14;            // 3D simple-cubic: 2 spin states x 7 up-counts
+constexpr int kMaxClasses = 14;
 constexpr uint32_t kRateOne = 1u << 28;  // rates are round(2^28 p)
 constexpr int kRateBits = 28;
 constexpr int64_t kTickInf = (int64_t)1 << 62;  // "no pending event"
@@ -14,6 +16,9 @@ constexpr int kEdges = 4;                // boundary lists: N, S, W, E
 enum Edge { kN = 0, kS = 1, kW = 2, kE = 3 };
 constexpr int kPosBits = 16;             // history entry = tick << 16 | position
 constexpr int kMaxHistCap = 1024;        // entries per boundary list, at most
+constexpr int kFaces3 = 6;               // 3D boundary lists: W, E, N, S, D, U
+enum Face3 { kFW = 0, kFE = 1, kFN = 2, kFS = 3, kFD = 4, kFU = 5 };
+constexpr int kMaxHistCap3 = 448;        // 3D: 18 lists of this length in LDS (< 64 KiB)
 
 // Per-subdomain state at committed time (or at a working window end).
 struct alignas(64) Carry {
@@ -76,10 +81,11 @@ struct IterFlags {
 // Everything one relaxation iteration of one lattice needs.
 struct Lattice {
   int32_t Lx, Ly, bx, by, nbx, nby, nsub;
+  int32_t Lz, bz, nbz;    // 3D simple-cubic lattice when Lz > 1 (else 1, 1, 1)
   int32_t S;              // sites per lane (power of 2, 1..16)
   int32_t sshift;         // log2(S)
   int32_t tick_bits;
-  uint32_t rate[kClasses];
+  uint32_t rate[kMaxClasses];  // 10 classes in 2D, 14 in 3D
   uint32_t seed_lo, seed_hi;
   int32_t hcap;           // entries per boundary list
   int32_t wcap;           // entries per subdomain window log
@@ -116,7 +122,7 @@ constexpr int kMaxBatch = 64;   // iterations queued per host round trip
 // Buffer q (0 or 1) of a double buffer.
 template <class LT>
 __host__ __device__ inline int8_t* spins_at(const LT& L, int q) {
-  return L.spins + (int64_t)(q & 1) * ((int64_t)L.Lx * L.Ly);
+  return L.spins + (int64_t)(q & 1) * ((int64_t)L.Lx * L.Ly * L.Lz);
 }
 template <class LT>
 __host__ __device__ inline Carry* carry_at(const LT& L, int q) { return L.carry + (q & 1) * L.nsub; }
@@ -207,6 +213,8 @@ struct BatchCounters {
 struct alignas(128) ShardRem {
   int32_t n;
 };
+// Persistent kernel instantiations (block shape class of a whole launch).
+enum { kBatchGeneric = 0, kBatch16NoWrap = 1 };
 struct BatchArgs {             // read-only for the kernel's lifetime
   BatchCounters* ctr;
   unsigned long long* q;       // kShards rings of qmask + 1 slots

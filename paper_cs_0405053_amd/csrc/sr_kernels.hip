@@ -25,235 +25,9 @@
 // Nothing on the event chain touches HBM except chunk refills and flushes.
 #include <vector>
 
-#include "sr_internal.h"
+#include "sr_device.h"
 
 namespace sr {
-
-// ------------------------------------------------------------ wave helpers
-__device__ __forceinline__ int lane_id() {
-  return (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
-}
-__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
-__device__ __forceinline__ uint32_t rdl(uint32_t v, int l) {
-  return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
-}
-__device__ __forceinline__ uint64_t rdl64(uint64_t v, int l) {
-  return (uint64_t)rdl((uint32_t)v, l) | ((uint64_t)rdl((uint32_t)(v >> 32), l) << 32);
-}
-__device__ __forceinline__ int ctz64(uint64_t m) { return __builtin_ctzll(m); }
-__device__ __forceinline__ int64_t min64(int64_t a, int64_t b) { return a < b ? a : b; }
-
-
-template <int CTRL, int ROWMASK>
-__device__ __forceinline__ uint32_t dpp0(uint32_t x) {
-  // lanes whose DPP source is outside the row (or whose row is masked off)
-  // read 0
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWMASK, 0xf, false);
-}
-
-// Inclusive prefix sum of 32-bit values over the 64 lanes.
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
-  x += dpp0<0x111, 0xf>(x);  // row_shr:1
-  x += dpp0<0x112, 0xf>(x);  // row_shr:2
-  x += dpp0<0x114, 0xf>(x);  // row_shr:4
-  x += dpp0<0x118, 0xf>(x);  // row_shr:8
-  x += dpp0<0x142, 0xa>(x);  // row_bcast:15 into rows 1, 3
-  x += dpp0<0x143, 0xc>(x);  // row_bcast:31 into rows 2, 3
-  return x;
-}
-
-// Inclusive prefix sum of 64-bit values within each row of 16 lanes.
-template <int SH>
-__device__ __forceinline__ uint64_t row_step64(uint64_t x) {
-  uint32_t lo = dpp0<0x110 + SH, 0xf>((uint32_t)x);
-  uint32_t hi = dpp0<0x110 + SH, 0xf>((uint32_t)(x >> 32));
-  return x + (((uint64_t)hi << 32) | lo);
-}
-__device__ __forceinline__ uint64_t row_incl_scan64(uint64_t x) {
-  x = row_step64<1>(x);
-  x = row_step64<2>(x);
-  x = row_step64<4>(x);
-  x = row_step64<8>(x);
-  return x;
-}
-
-// ------------------------------------------------------------ random numbers
-// Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), written from its
-// published round function: multipliers 0xD2511F53 / 0xCD9E8D57, key
-// increments 0x9E3779B9 / 0xBB67AE85.
-__device__ __forceinline__ void philox4x32_10(uint32_t k0, uint32_t k1, uint32_t& c0,
-                                              uint32_t& c1, uint32_t& c2, uint32_t& c3) {
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
-    uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-    uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
-    uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
-  }
-}
-
-// -ln(U), U = (u|1)/2^64, as an integer in units of 2^-(28+tick_bits):
-// binary logarithm of the normalised mantissa by 32 repeated squarings of a
-// truncated Q1.31 value, then one 64x64->128 product with floor(ln2 * 2^64).
-__device__ __forceinline__ uint64_t neglog_fixed(uint64_t u, int tick_bits) {
-  const uint64_t kLn2Q64 = 0xB17217F7D1CF79ABull;
-  uint64_t m = u | 1ull;
-  int c = __clzll((long long)m);
-  int e = 63 - c;
-  uint32_t z = (uint32_t)((m << c) >> 32);
-  uint32_t frac = 0;
-#pragma unroll 8
-  for (int i = 0; i < 32; ++i) {
-    uint64_t q = (uint64_t)z * (uint64_t)z;
-    uint32_t bit = (uint32_t)(q >> 63);
-    frac = (frac << 1) | bit;
-    z = (uint32_t)(q >> (31 + bit));
-  }
-  uint64_t lq = ((uint64_t)(64 - e) << 32) - (uint64_t)frac;
-  uint64_t lo = lq * kLn2Q64, hi = __umul64hi(lq, kLn2Q64);
-  int sh = 96 - (kRateBits + tick_bits);  // 40 .. 64
-  return sh >= 64 ? (hi >> (sh - 64)) : ((hi << (64 - sh)) | (lo >> sh));
-}
-
-// The 64 pairs (E_j, V_j), j = j0 + lane, of subdomain d.
-__device__ __forceinline__ void draw_chunk(uint32_t k0, uint32_t k1, uint64_t j0, uint32_t d,
-                                           int lane, int tick_bits, uint64_t& E, uint64_t& V) {
-  uint64_t j = j0 + (uint64_t)lane;
-  uint32_t c0 = (uint32_t)j, c1 = (uint32_t)(j >> 32), c2 = d, c3 = 0;
-  philox4x32_10(k0, k1, c0, c1, c2, c3);
-  V = (uint64_t)c2 | ((uint64_t)c3 << 32);
-  E = neglog_fixed((uint64_t)c0 | ((uint64_t)c1 << 32), tick_bits);
-}
-
-// ------------------------------------------------------------ integer time
-// floor(n / d) and ceil(n / d) for d >= 1, exact when the quotient is below
-// 2^50: a double estimate from the hardware reciprocal refined by one Newton
-// step (no IEEE division sequence), then exact integer correction.  Larger
-// quotients are reported as 2^50, which callers treat as "beyond any
-// horizon" (horizons are below 2^46 ticks, so an estimate near that bound
-// that lands on either side gives the same behaviour).
-__device__ __forceinline__ uint64_t udiv_floor(uint64_t n, uint64_t d, uint64_t* rem_nonzero) {
-  const double dd = (double)d;
-  double r = __builtin_amdgcn_rcp(dd);
-  r = __builtin_fma(r, __builtin_fma(-dd, r, 1.0), r);
-  const double qd = (double)n * r;
-  if (qd >= 1125899906842624.0) { *rem_nonzero = 1; return 1ull << 50; }
-  uint64_t q = (uint64_t)qd;
-  uint64_t p = q * d;
-  while (p > n) { q -= 1; p -= d; }
-  while (n - p >= d) { q += 1; p += d; }
-  *rem_nonzero = (n != p);
-  return q;
-}
-
-// floor(n / d) for a quotient below 2^20 (the index of a site inside its
-// class): a single-precision estimate, then exact integer correction.
-__device__ __forceinline__ uint32_t udiv_small(uint64_t n, uint32_t d) {
-  float qf = (float)n * __builtin_amdgcn_rcpf((float)d);
-  uint32_t q = (uint32_t)qf;
-  uint64_t p = (uint64_t)q * d;
-  while (p > n) { q -= 1; p -= d; }
-  while (n - p >= d) { q += 1; p += d; }
-  return q;
-}
-
-// Tick of the pending event: anchor + max(1, ceil((E - acc) / lam)), or never
-// when lam = 0 (eq. nextau, and eq. lambdataua after a break point).
-__device__ __forceinline__ int64_t next_tick(int64_t anchor, uint64_t E, uint64_t acc, uint64_t lam) {
-  if (lam == 0) return kTickInf;
-  uint64_t nz;
-  uint64_t q = udiv_floor(E - acc, lam, &nz);
-  if (q >= (1ull << 50)) return kTickInf;
-  q += nz;
-  if (q < 1) q = 1;
-  return anchor + (int64_t)q;
-}
-
-// ------------------------------------------------------------ lists
-// The four neighbour lists of a subdomain are merged, once per run, into one
-// stream sorted by (tick, edge) in LDS; an entry is tick << 18 | edge << 16 |
-// position.  The event loop reads it through a 64-entry register window.
-constexpr int kKeyShift = 18;
-
-// Number of keys < k in the sorted LDS array a[0, n).
-__device__ __forceinline__ int lds_lower_bound(const uint64_t* a, int n, uint64_t k) {
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    int mid = (lo + hi) >> 1;
-    if (a[mid] < k) lo = mid + 1; else hi = mid;
-  }
-  return lo;
-}
-
-struct Merged {
-  const uint64_t* m;   // LDS
-  int n, head;
-  uint64_t chunk;
-  int64_t ht;          // tick of the head entry, kTickInf when exhausted
-};
-__device__ __forceinline__ void merged_open(Merged& s, const uint64_t* m, int n, int head, int lane) {
-  s.m = m; s.n = n; s.head = head;
-  int b = head & ~63;
-  s.chunk = (b + lane < n) ? m[b + lane] : ~0ull;
-  s.ht = head < n ? (int64_t)(rdl64(s.chunk, head & 63) >> kKeyShift) : kTickInf;
-}
-__device__ __forceinline__ uint64_t merged_pop(Merged& s, int lane) {
-  uint64_t e = rdl64(s.chunk, s.head & 63);
-  s.head++;
-  if (s.head >= s.n) {
-    s.ht = kTickInf;
-  } else {
-    if ((s.head & 63) == 0) s.chunk = (s.head + lane < s.n) ? s.m[s.head + lane] : ~0ull;
-    s.ht = (int64_t)(rdl64(s.chunk, s.head & 63) >> kKeyShift);
-  }
-  return e;
-}
-
-// First tick at which the own list of this run (`cur`, n entries) differs
-// from the previous iteration's (`prev`, np entries); both agree on their
-// first n0 entries.  kTickInf if equal.  Both lists are in this wave's LDS.
-__device__ __forceinline__ int64_t first_change(const uint64_t* cur, int n, const uint64_t* prev, int np,
-                                                int n0, int lane) {
-  const int m = n < np ? n : np;
-  for (int b = n0 & ~63; b < m; b += 64) {
-    int i = b + lane;
-    bool diff = false;
-    uint64_t x = 0, y = 0;
-    if (i >= n0 && i < m) {
-      x = cur[i];
-      y = prev[i];
-      diff = x != y;
-    }
-    uint64_t dm = ballot(diff);
-    if (dm) {
-      int f = ctz64(dm);
-      uint64_t xf = rdl64(x, f), yf = rdl64(y, f);
-      int64_t tx = (int64_t)(xf >> kPosBits), ty = (int64_t)(yf >> kPosBits);
-      return tx < ty ? tx : ty;
-    }
-  }
-  if (n == np) return kTickInf;
-  // one list is a prefix of the other: the first extra entry
-  const uint64_t e = n > np ? cur[m] : prev[m];
-  return (int64_t)(e >> kPosBits);
-}
-
-// SplitMix64 finaliser (Steele, Lea & Flood 2014) for event digests.
-__device__ __forceinline__ uint64_t mix64(uint64_t z) {
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
-__device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
-  for (int off = 32; off >= 1; off >>= 1) {
-    uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, off, 64);
-    uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), off, 64);
-    x += ((uint64_t)hi << 32) | lo;
-  }
-  return x;
-}
 
 // LDS bytes one relaxation wave needs: the halo tile, or the lists
 // (whichever is larger): the four raw neighbour lists (reused for the own
@@ -1062,7 +836,12 @@ constexpr uint32_t kProgressEvery = 4096;
 // finishes its current task before it waits.  Registers are capped so that
 // six waves share a SIMD (80 VGPRs and a few spills instead of 105, i.e. four
 // waves): more waves hide more of each task's latency chain.
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void batch_kernel(BatchArgs B) {
+// BX, BY, NW as for the plain kernels: <16, 16, true> (constant index
+// arithmetic, no wrap handling) for launches of large lattices that all have
+// 16x16 blocks and two or more subdomains per direction, <0, 0, false>
+// otherwise; WPE caps the waves per SIMD (registers per wave).
+template <int BX, int BY, bool NW, int WPE>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void batch_kernel(BatchArgs B) {
   extern __shared__ int8_t tile[];
   const int lane = lane_id();
   CLattice* lats = (CLattice*)B.lat;
@@ -1109,7 +888,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void ba
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     LatRun* run = &B.run[lat];
     const Step st = step_of(load_run(run, lane));
-    relax_subdomain<0, 0>(lats[lat], st, d, tile, &run->fl);
+    relax_subdomain<BX, BY, NW>(lats[lat], st, d, tile, &run->fl);
     // The run ends, and the count below starts, with a lane-0 region; left
     // alone the compiler merges the two and duplicates the release into both
     // paths, i.e. two L2 write-backs per task (40% of the batched form's
@@ -1181,6 +960,11 @@ __global__ __launch_bounds__(256) void observables_kernel(const int8_t* s, int L
 }
 
 // ------------------------------------------------------------ launchers
+// 3D lattices (sr_kernels3d.hip)
+hipError_t launch_relax3d(const Lattice& L, const Step& st, hipStream_t stream);
+const void* relax3d_graph_kernel_ptr();
+size_t relax3d_lds(const Lattice& L);
+
 // The instantiation for a lattice's block shape and wrap: 16x16 and 32x32
 // blocks have their own, split by whether a block can wrap onto itself.
 static bool no_wrap(const Lattice& L) { return L.nbx > 1 && L.nby > 1; }
@@ -1191,6 +975,7 @@ static const void* relax_kernel_for(const Lattice& L) {
   return (const void*)relax_kernel<0, 0, false>;
 }
 static const void* relax_graph_kernel_for(const Lattice& L) {
+  if (L.Lz > 1) return relax3d_graph_kernel_ptr();
   const bool nw = no_wrap(L);
   if (L.bx == 16 && L.by == 16)
     return nw ? (const void*)relax_graph_kernel<16, 16, true> : (const void*)relax_graph_kernel<16, 16, false>;
@@ -1199,7 +984,12 @@ static const void* relax_graph_kernel_for(const Lattice& L) {
   return (const void*)relax_graph_kernel<0, 0, false>;
 }
 
+size_t relax_lds(const Lattice& L) {
+  return L.Lz > 1 ? relax3d_lds(L) : relax_lds_bytes(L.bx, L.by, L.hcap);
+}
+
 hipError_t launch_relax(const Lattice& L, const Step& st, hipStream_t stream) {
+  if (L.Lz > 1) return launch_relax3d(L, st, stream);
   size_t lds = relax_lds_bytes(L.bx, L.by, L.hcap);
   Lattice Lc = L;
   Step sc = st;
@@ -1229,7 +1019,7 @@ hipError_t build_window_graph(const Lattice& L, const Step* dstep, int k, hipGra
   Lattice Lc = L;
   const Step* sp = dstep;
   std::vector<int> idx(k);
-  size_t lds = relax_lds_bytes(L.bx, L.by, L.hcap);
+  size_t lds = relax_lds(L);
   for (int i = 0; i < k && e == hipSuccess; ++i) {
     idx[i] = i;
     void* rargs[] = {&Lc, &sp, &idx[i]};
@@ -1265,16 +1055,24 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t stream) {
   return hipGetLastError();
 }
 
-hipError_t launch_batch(const BatchArgs& B, int waves, size_t lds, hipStream_t stream) {
-  hipLaunchKernelGGL(batch_kernel, dim3(waves), dim3(64), lds, stream, B);
-  return hipGetLastError();
+// The compile-time 16x16 body needs 121 VGPRs inside the task loop: capped at
+// four waves per SIMD it runs without spills (at six it spills 124 B per
+// lane and is slower).  The runtime-shape kernel keeps six waves.
+static const void* batch_kernel_for(int shape) {
+  return shape == kBatch16NoWrap ? (const void*)batch_kernel<16, 16, true, 4> : (const void*)batch_kernel<0, 0, false, 6>;
 }
 
-size_t relax_lds(const Lattice& L) { return relax_lds_bytes(L.bx, L.by, L.hcap); }
+hipError_t launch_batch(const BatchArgs& B, int shape, int waves, size_t lds, hipStream_t stream) {
+  BatchArgs Bc = B;
+  void* args[] = {&Bc};
+  const hipError_t e = hipLaunchKernel(batch_kernel_for(shape), dim3(waves), dim3(64), args, lds, stream);
+  return e != hipSuccess ? e : hipGetLastError();
+}
 
-int batch_waves_per_cu(size_t lds) {
+
+int batch_waves_per_cu(int shape, size_t lds) {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel, 64, lds) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel_for(shape), 64, lds) != hipSuccess) return 0;
   return n;
 }
 

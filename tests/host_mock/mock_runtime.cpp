@@ -145,7 +145,14 @@ hipError_t launch_observables(const int8_t* s, int Lx, int Ly, unsigned long lon
   out[1] = 0;
   return hipSuccess;
 }
-hipError_t launch_batch(const BatchArgs& B, int, size_t, hipStream_t) {
+hipError_t launch_observables3d(const int8_t* s, int Lx, int Ly, int Lz, unsigned long long* out, hipStream_t) {
+  long long m = 0;
+  for (int64_t i = 0; i < (int64_t)Lx * Ly * Lz; ++i) m += s[i];
+  out[0] = (unsigned long long)m;
+  out[1] = 0;
+  return hipSuccess;
+}
+hipError_t launch_batch(const BatchArgs& B, int, int, size_t, hipStream_t) {
   const int G = env_int("SR_MOCK_G", 1);
   for (uint32_t k = 0; k < B.nlat; ++k) {
     LatRun& r = B.run[k];
@@ -179,7 +186,7 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t) {
   std::memset(p, 0, bytes);
   return hipSuccess;
 }
-int batch_waves_per_cu(size_t) { return 4; }
+int batch_waves_per_cu(int, size_t) { return 4; }
 size_t relax_lds(const Lattice& L) { return 1024 + 64 * (size_t)L.hcap; }
 hipError_t build_window_graph(const Lattice& L, const Step* dstep, int k, hipGraphExec_t* out) {
   *out = new ihipGraphExec_t{L, dstep, k};

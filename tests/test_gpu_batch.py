@@ -183,3 +183,31 @@ def test_batched_wipe_step_rule_equals_oracle():
         assert np.array_equal(s.digests()[0], ref["sub_digest"]), p
         assert np.array_equal(s.carry(), ref["carry"][:, :3]), p
         s.close()
+
+
+@pytest.mark.parametrize("kernel", ["16x16", "generic"])
+def test_both_persistent_kernels_equal_plain_and_oracle(monkeypatch, kernel):
+    # lattices that all have 16x16 blocks without self-wrap can run on the
+    # compile-time 16x16 persistent kernel; both kernels must give the plain
+    # result (the library reads SR_BATCH_KERNEL at each batched launch)
+    sr = _sr()
+    rng = np.random.default_rng(21)
+    ps = [W.params(L, L, 16, 16, T=float(rng.uniform(1.0, 3.5)), h=float(rng.uniform(-0.2, 0.2)),
+                   window=[0.5, 1.0][i % 2], horizon=3.0, seed=900 + i, log_mode="digest")
+          for i, L in enumerate([32, 48, 64, 96, 128, 160])]
+    plain = []
+    for p in ps:
+        s = sr.Sim(p)
+        s.run()
+        plain.append(state(s))
+        s.close()
+    monkeypatch.setenv("SR_BATCH_KERNEL", kernel)
+    sims = [sr.Sim(p) for p in ps]
+    sr.batch_run(sims)
+    for i, (p, s) in enumerate(zip(ps, sims)):
+        assert same(state(s), plain[i]), (kernel, i)
+    ref = oracle.des(ps[3], log=False)
+    assert np.array_equal(sims[3].spins(), ref["spins"])
+    assert np.array_equal(sims[3].digests()[0], ref["sub_digest"])
+    for s in sims:
+        s.close()
