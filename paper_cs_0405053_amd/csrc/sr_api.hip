@@ -35,7 +35,8 @@ hipError_t launch_observables3d(const int8_t* s, int Lx, int Ly, int Lz, unsigne
                                 hipStream_t stream);
 hipError_t launch_batch(const BatchArgs& B, int shape, int waves, size_t lds, hipStream_t stream);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t stream);
-hipError_t build_window_graph(const Lattice& L, const Step* dstep, int k, hipGraphExec_t* out);
+const void* clear_flags_kernel_ptr();
+const void* relax_graph_kernel_ptr(const Lattice& L);
 int batch_waves_per_cu(int shape, size_t lds);
 size_t relax_lds(const Lattice& L);
 }  // namespace sr
@@ -505,6 +506,49 @@ static int commit(sr_sim* s) {
   s->st.t_c = s->st.t_end;
   s->windows++;
   return SR_OK;
+}
+
+// A graph of k iterations of one window: clear the flags, then k relaxation
+// kernels in sequence.  Node i reads the window descriptor from dstep
+// (written before every replay) and is iteration dstep->it + i.  Kernel-node
+// arguments are copied when a node is added, so they may live on the stack.
+static hipError_t build_window_graph(const Lattice& L, const Step* dstep, int k, hipGraphExec_t* out) {
+  hipGraph_t g = nullptr;
+  hipError_t e = hipGraphCreate(&g, 0);
+  if (e != hipSuccess) return e;
+  hipGraphNode_t prev = nullptr, node = nullptr;
+  IterFlags* fl = L.flags;
+  int nclear = k;
+  void* cargs[] = {&fl, &nclear};
+  hipKernelNodeParams kp = {};
+  kp.func = const_cast<void*>(clear_flags_kernel_ptr());
+  kp.gridDim = dim3(1);
+  kp.blockDim = dim3(kMaxBatch);
+  kp.sharedMemBytes = 0;
+  kp.kernelParams = cargs;
+  kp.extra = nullptr;
+  e = hipGraphAddKernelNode(&node, g, nullptr, 0, &kp);
+  prev = node;
+  Lattice Lc = L;
+  const Step* sp = dstep;
+  std::vector<int> idx(k);
+  const size_t lds = relax_lds(L);
+  for (int i = 0; i < k && e == hipSuccess; ++i) {
+    idx[i] = i;
+    void* rargs[] = {&Lc, &sp, &idx[i]};
+    hipKernelNodeParams rp = {};
+    rp.func = const_cast<void*>(relax_graph_kernel_ptr(L));
+    rp.gridDim = dim3(L.nsub);
+    rp.blockDim = dim3(64);
+    rp.sharedMemBytes = (unsigned)lds;
+    rp.kernelParams = rargs;
+    rp.extra = nullptr;
+    e = hipGraphAddKernelNode(&node, g, &prev, 1, &rp);
+    prev = node;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  return e;
 }
 
 // One window of the Sec. 4 box.  Iterations are queued K at a time on the

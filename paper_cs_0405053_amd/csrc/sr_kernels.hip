@@ -997,46 +997,10 @@ hipError_t launch_relax(const Lattice& L, const Step& st, hipStream_t stream) {
   return hipLaunchKernel(relax_kernel_for(L), dim3(L.nsub), dim3(64), args, lds, stream);
 }
 
-// A graph of k iterations of one window: clear the flags, then k relaxation
-// kernels in sequence.
-hipError_t build_window_graph(const Lattice& L, const Step* dstep, int k, hipGraphExec_t* out) {
-  hipGraph_t g = nullptr;
-  hipError_t e = hipGraphCreate(&g, 0);
-  if (e != hipSuccess) return e;
-  hipGraphNode_t prev = nullptr, node = nullptr;
-  IterFlags* fl = L.flags;
-  int nclear = k;
-  void* cargs[] = {&fl, &nclear};
-  hipKernelNodeParams kp = {};
-  kp.func = (void*)clear_flags_kernel;
-  kp.gridDim = dim3(1);
-  kp.blockDim = dim3(kMaxBatch);
-  kp.sharedMemBytes = 0;
-  kp.kernelParams = cargs;
-  kp.extra = nullptr;
-  e = hipGraphAddKernelNode(&node, g, nullptr, 0, &kp);
-  prev = node;
-  Lattice Lc = L;
-  const Step* sp = dstep;
-  std::vector<int> idx(k);
-  size_t lds = relax_lds(L);
-  for (int i = 0; i < k && e == hipSuccess; ++i) {
-    idx[i] = i;
-    void* rargs[] = {&Lc, &sp, &idx[i]};
-    hipKernelNodeParams rp = {};
-    rp.func = const_cast<void*>(relax_graph_kernel_for(L));
-    rp.gridDim = dim3(L.nsub);
-    rp.blockDim = dim3(64);
-    rp.sharedMemBytes = (unsigned)lds;
-    rp.kernelParams = rargs;
-    rp.extra = nullptr;
-    e = hipGraphAddKernelNode(&node, g, &prev, 1, &rp);
-    prev = node;
-  }
-  if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(g);
-  return e;
-}
+// Entry points of the graph form (the host runtime builds the window graphs
+// from them).
+const void* clear_flags_kernel_ptr() { return (const void*)clear_flags_kernel; }
+const void* relax_graph_kernel_ptr(const Lattice& L) { return relax_graph_kernel_for(L); }
 
 // Zeroes `bytes` (a multiple of 16) at a 16-byte aligned address: a kernel,
 // so that no memset is issued for the batch queue.

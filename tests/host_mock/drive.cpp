@@ -267,6 +267,38 @@ static void threads() {
   for (auto& x : th) x.join();
 }
 
+// The plain comparison of the batch workload: 8 host threads, each driving
+// its share of 64 simulations on its own stream, window graphs built,
+// replayed, dropped and rebuilt as lists grow (SR_MOCK_REGROW), then all
+// destroyed; graph nodes carry arguments that lived on the builder's stack.
+static void graph_threads() {
+  const int nth = 8, per = 8;
+  std::vector<std::vector<sr_sim*>> sims(nth);
+  std::vector<std::thread> th;
+  for (int t = 0; t < nth; ++t) {
+    th.emplace_back([t, &sims]() {
+      for (int i = 0; i < per; ++i) {
+        sr_params p = params(32 + 16 * ((t * per + i) % 6), (t + i) % 3 ? 0.0 : 0.5, 2.0 + 0.5 * (i % 4),
+                             1000 * t + i);
+        sr_sim* s = nullptr;
+        CHECK(sr_create(&p, nullptr, &s) == SR_OK);
+        sims[t].push_back(s);
+      }
+      for (int rep = 0; rep < 2; ++rep)
+        for (sr_sim* s : sims[t]) {
+          CHECK(sr_reset(s) == SR_OK);
+          int32_t done = 0;
+          CHECK(sr_run_window(s, -1, nullptr, &done) == SR_OK && done > 0);
+          sr_obs o;
+          CHECK(sr_observables(s, &o) == SR_OK && o.tick == o.horizon_ticks);
+        }
+    });
+  }
+  for (auto& x : th) x.join();
+  for (auto& v : sims)
+    for (sr_sim* s : v) sr_destroy(s);
+}
+
 int main(int argc, char** argv) {
   if (argc < 2) return 2;
   const char* w = argv[1];
@@ -276,6 +308,7 @@ int main(int argc, char** argv) {
   else if (!std::strcmp(w, "errors")) errors();
   else if (!std::strcmp(w, "threads")) threads();
   else if (!std::strcmp(w, "static")) static_step();
+  else if (!std::strcmp(w, "graph_threads")) graph_threads();
   else return 2;
   CHECK(sr_mock_live_allocations() == 0);
   std::printf("ok %s\n", w);

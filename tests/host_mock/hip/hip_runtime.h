@@ -42,6 +42,11 @@ const char* hipGetErrorString(hipError_t);
 hipError_t hipGetLastError();
 hipError_t hipGetDevice(int*);
 hipError_t hipDeviceGetAttribute(int*, hipDeviceAttribute_t, int);
+hipError_t hipGraphCreate(hipGraph_t* g, unsigned flags);
+hipError_t hipGraphAddKernelNode(hipGraphNode_t* node, hipGraph_t g, const hipGraphNode_t* deps, size_t ndeps,
+                                 const hipKernelNodeParams* p);
+hipError_t hipGraphInstantiate(hipGraphExec_t* e, hipGraph_t g, hipGraphNode_t* err_node, char* log, size_t n);
+hipError_t hipGraphDestroy(hipGraph_t g);
 hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t);
 hipError_t hipGetSymbolAddress(void** p, const void* symbol);
 hipError_t hipGraphExecDestroy(hipGraphExec_t);

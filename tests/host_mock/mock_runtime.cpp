@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <mutex>
 #include <set>
+#include <vector>
 
 #include "../../paper_cs_0405053_amd/csrc/sr_internal.h"
 
@@ -84,32 +85,112 @@ hipError_t hipGetSymbolAddress(void** p, const void* symbol) {
 }
 hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t, int) { *v = 256; return hipSuccess; }
 
-// A "graph" of k relaxation iterations: remembers the lattice descriptor and
-// where the window descriptor lives, as the captured kernels do.
-struct ihipGraphExec_t {
-  sr::Lattice L;
-  const sr::Step* dstep;
-  int k;
+// Graphs.  A kernel node copies its arguments when it is added (as HIP
+// does), interpreted by the stand-in kernel it names; an instantiated graph
+// replays its nodes in order.  Graph objects are tracked like allocations.
+static char g_clear_kernel, g_relax_kernel;          // stand-in kernel addresses
+struct MockNode {
+  int kind;                 // 0 = clear flags, 1 = relaxation iteration
+  sr::IterFlags* flags;     // clear: first flag entry
+  int n;                    // clear: entries; relax: node index i
+  sr::Lattice L;            // relax: lattice descriptor (by value)
+  const sr::Step* step;     // relax: window descriptor, read at replay
 };
-static void relax_flags(sr::IterFlags* f, int it) {
+struct ihipGraphNode_t { int index; };
+struct ihipGraph_t { std::vector<MockNode> nodes; std::vector<ihipGraphNode_t*> handles; };
+struct ihipGraphExec_t { std::vector<MockNode> nodes; };
+static std::set<void*> g_graphs, g_execs;
+
+static void relax_flags(sr::IterFlags* f, int it, const sr::Lattice& L) {
   std::memset(f, 0, sizeof(*f));
   f->changed = it < env_int("SR_MOCK_G", 1) - 1;
+  // SR_MOCK_REGROW=1: the boundary lists of a lattice overflow until they
+  // hold 128 entries (the host grows them, dropping and rebuilding graphs)
+  if (env_int("SR_MOCK_REGROW", 0) && L.hcap < 128) f->ovf_hist = 1;
 }
 static void count_runs(const sr::Lattice& L) {
   for (int d = 0; d < L.nsub; ++d) L.stat[d].runs += 1;
 }
-// Iterations queued behind one that converged do nothing, as on the device.
-static bool queued_after_convergence(const sr::IterFlags* f, int fi) { return fi > 0 && !f[fi - 1].changed; }
-hipError_t hipGraphLaunch(hipGraphExec_t g, hipStream_t) {
-  for (int i = 0; i < g->k; ++i) {
-    if (queued_after_convergence(g->L.flags, i)) continue;
-    relax_flags(&g->L.flags[i], g->dstep->it + i);
-    count_runs(g->L);
+// Iterations queued behind one that converged (or overflowed) do nothing, as
+// on the device.
+static bool queued_after_convergence(const sr::IterFlags* f, int fi) {
+  return fi > 0 && (!f[fi - 1].changed || f[fi - 1].ovf_hist || f[fi - 1].ovf_log);
+}
+
+hipError_t hipGraphCreate(hipGraph_t* g, unsigned) {
+  *g = new ihipGraph_t();
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_graphs.insert(*g);
+  return hipSuccess;
+}
+hipError_t hipGraphAddKernelNode(hipGraphNode_t* node, hipGraph_t g, const hipGraphNode_t* deps, size_t ndeps,
+                                 const hipKernelNodeParams* p) {
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_graphs.count(g)) { std::fprintf(stderr, "node added to unknown graph\n"); std::abort(); }
+  }
+  // the library builds chains: each node depends on the one before
+  if (g->nodes.empty() ? ndeps != 0 : (ndeps != 1 || deps[0] != g->handles.back())) {
+    std::fprintf(stderr, "graph node dependencies are not a chain\n");
+    std::abort();
+  }
+  MockNode n{};
+  if (p->func == &g_clear_kernel) {
+    n.kind = 0;
+    n.flags = *(sr::IterFlags**)p->kernelParams[0];
+    n.n = *(int*)p->kernelParams[1];
+  } else if (p->func == &g_relax_kernel) {
+    n.kind = 1;
+    n.L = *(sr::Lattice*)p->kernelParams[0];
+    n.step = *(const sr::Step**)p->kernelParams[1];
+    n.n = *(int*)p->kernelParams[2];
+  } else {
+    std::fprintf(stderr, "unknown kernel in graph node\n");
+    std::abort();
+  }
+  g->nodes.push_back(n);
+  g->handles.push_back(new ihipGraphNode_t{(int)g->nodes.size() - 1});
+  *node = g->handles.back();
+  return hipSuccess;
+}
+hipError_t hipGraphInstantiate(hipGraphExec_t* e, hipGraph_t g, hipGraphNode_t*, char*, size_t) {
+  *e = new ihipGraphExec_t{g->nodes};
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_execs.insert(*e);
+  return hipSuccess;
+}
+hipError_t hipGraphDestroy(hipGraph_t g) {
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_graphs.erase(g)) { std::fprintf(stderr, "hipGraphDestroy of unknown graph\n"); std::abort(); }
+  }
+  for (auto* h : g->handles) delete h;
+  delete g;
+  return hipSuccess;
+}
+hipError_t hipGraphLaunch(hipGraphExec_t e, hipStream_t) {
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_execs.count(e)) { std::fprintf(stderr, "hipGraphLaunch of unknown graph\n"); std::abort(); }
+  }
+  for (const MockNode& n : e->nodes) {
+    if (n.kind == 0) {
+      std::memset(n.flags, 0, (size_t)n.n * sizeof(sr::IterFlags));
+    } else {
+      const int i = n.n;
+      if (queued_after_convergence(n.L.flags, i)) continue;
+      relax_flags(&n.L.flags[i], n.step->it + i, n.L);
+      count_runs(n.L);
+    }
   }
   return hipSuccess;
 }
-hipError_t hipGraphExecDestroy(hipGraphExec_t g) {
-  delete g;
+hipError_t hipGraphExecDestroy(hipGraphExec_t e) {
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_execs.erase(e)) { std::fprintf(stderr, "hipGraphExecDestroy of unknown graph\n"); std::abort(); }
+  }
+  delete e;
   return hipSuccess;
 }
 
@@ -120,13 +201,13 @@ extern "C" size_t sr_mock_malloc_calls() {
 
 extern "C" size_t sr_mock_live_allocations() {
   std::lock_guard<std::mutex> g(g_mu);
-  return g_dev.size() + g_host.size() + g_ev.size();
+  return g_dev.size() + g_host.size() + g_ev.size() + g_graphs.size() + g_execs.size();
 }
 
 namespace sr {
 hipError_t launch_relax(const Lattice& L, const Step& st, hipStream_t) {
   if (queued_after_convergence(L.flags, st.fi)) return hipSuccess;
-  relax_flags(&L.flags[st.fi], st.it);
+  relax_flags(&L.flags[st.fi], st.it, L);
   count_runs(L);
   return hipSuccess;
 }
@@ -188,8 +269,6 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t) {
 }
 int batch_waves_per_cu(int, size_t) { return 4; }
 size_t relax_lds(const Lattice& L) { return 1024 + 64 * (size_t)L.hcap; }
-hipError_t build_window_graph(const Lattice& L, const Step* dstep, int k, hipGraphExec_t* out) {
-  *out = new ihipGraphExec_t{L, dstep, k};
-  return hipSuccess;
-}
+const void* clear_flags_kernel_ptr() { return &g_clear_kernel; }
+const void* relax_graph_kernel_ptr(const Lattice&) { return &g_relax_kernel; }
 }  // namespace sr

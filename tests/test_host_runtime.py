@@ -101,3 +101,17 @@ def test_threads_without_data_races(drive_tsan):
     r = subprocess.run([drive_tsan, "threads"], capture_output=True, text=True, timeout=300,
                        env=dict(os.environ, SR_MOCK_G="3", TSAN_OPTIONS="halt_on_error=1"))
     assert r.returncode == 0 and "ok threads" in r.stdout, (r.stdout + r.stderr)[-4000:]
+
+
+@pytest.mark.parametrize("regrow", [0, 1])
+def test_window_graphs_from_eight_threads(drive, regrow):
+    # the library's own graph building (kernel nodes whose arguments live on
+    # the builder's stack, graphs dropped and rebuilt when lists grow) under
+    # AddressSanitizer, from eight threads at once
+    run(drive, "graph_threads", SR_MOCK_G=5, SR_MOCK_REGROW=regrow)
+
+
+def test_window_graphs_from_eight_threads_without_races(drive_tsan):
+    r = subprocess.run([drive_tsan, "graph_threads"], capture_output=True, text=True, timeout=300,
+                       env=dict(os.environ, SR_MOCK_G="5", SR_MOCK_REGROW="1", TSAN_OPTIONS="halt_on_error=1"))
+    assert r.returncode == 0 and "ok graph_threads" in r.stdout, (r.stdout + r.stderr)[-4000:]
