@@ -263,15 +263,20 @@ int sr_tune(const sr_params* p, int32_t* bx, int32_t* by, double* window);
 
 /* ---- serving: continuous batching of simulation requests ----
  * Driven by the caller (no threads).  sr_server_submit queues a request (an
- * SR_LOG_DIGEST simulation).  Each sr_server_pump is one scheduling round:
- * admit queued requests in arrival order while their device footprint fits
- * `hbm_budget` bytes, run one persistent batch step (sr_batch_step) over all
- * admitted lattices, each committing at most `windows_per_round` windows, and
- * retire the lattices that reached their horizon (results to sr_server_poll),
- * which frees memory for the next round.  Requests submitted between rounds
- * join the next one; their work overlaps on the device with the requests
- * already running.  A request's result equals its simulation run alone.
- * Not thread-safe: one thread drives a server. */
+ * SR_LOG_DIGEST simulation of a 2D lattice).  The server keeps one persistent
+ * batched launch running over every admitted lattice; sr_server_pump never
+ * waits for it to finish.  While it runs, a pump that sees a waiting request
+ * whose device footprint fits `hbm_budget`, or a lattice that reached its
+ * horizon, asks the launch to end (every lattice pauses at its next window
+ * boundary, so the launch ends within about one window of work); the pump
+ * after it ends retires finished lattices (results to sr_server_poll, memory
+ * freed), admits waiting requests in arrival order while their footprint
+ * fits, and starts the next launch over all admitted lattices.  A request
+ * thus joins the lattices already on the device after the windows in flight,
+ * not after a round of fixed length, and its work overlaps theirs.  A
+ * request's result equals its simulation run alone (pausing at a window
+ * boundary does not change the trajectory).  Not thread-safe: one thread
+ * drives a server. */
 typedef struct sr_server sr_server;
 typedef struct {
   uint64_t req_id;           /* from sr_server_submit */
@@ -289,12 +294,16 @@ typedef struct {
   double busy_s, uptime_s;   /* time inside batch steps / since creation */
 } sr_server_info;
 
-/* hip_stream: stream for all of the server's device work (NULL = default). */
+/* hip_stream: stream for all of the server's device work (NULL = default).
+ * windows_per_round > 0 additionally ends every launch after that many
+ * windows per lattice (a fairness bound); <= 0: launches end only when asked
+ * to or when every lattice is done. */
 int sr_server_create(size_t hbm_budget, int32_t windows_per_round, void* hip_stream, sr_server** out);
 /* Copies the parameters (and SR_INIT_USER spins); the arrival time is now.
  * SR_ENOMEM if the request alone exceeds the budget. */
 int sr_server_submit(sr_server* v, const sr_params* p, uint64_t* req_id);
-/* One round (see above); *n_open (may be NULL) = requests not yet retired. */
+/* One scheduling step (see above); waits at most about a millisecond for a
+ * running launch.  *n_open (may be NULL) = requests not yet retired. */
 int sr_server_pump(sr_server* v, int32_t* n_open);
 /* Retired requests since the last poll, oldest first; up to cap into the
  * caller's array, *n = how many. */

@@ -349,11 +349,12 @@ def batch_run(sims: Sequence[Sim], stream=None) -> None:
 
 class Server:
     """Continuous-batching request loop, driven by the caller: `submit`
-    queues a request, every `pump` is one round (admit by HBM footprint, one
-    persistent batch step over all admitted lattices, retire finished ones),
-    `poll` returns retired results."""
+    queues a request; `pump` keeps one persistent launch running over the
+    admitted lattices, ends it at the next window boundaries when a request
+    can be admitted or a lattice finished, then retires, admits by HBM
+    footprint and relaunches; `poll` returns retired results."""
 
-    def __init__(self, hbm_budget: int, windows_per_round: int = 8, stream=None):
+    def __init__(self, hbm_budget: int, windows_per_round: int = 0, stream=None):
         h = C.c_void_p()
         rc = lib().sr_server_create(int(hbm_budget), int(windows_per_round), _stream_ptr(stream),
                                     C.byref(h))
@@ -371,7 +372,9 @@ class Server:
         return int(rid.value)
 
     def pump(self) -> int:
-        """One scheduling round; returns the requests not yet retired."""
+        """One scheduling step (retire, admit, (re)launch, or ask the running
+        launch to end at the next window boundaries); waits at most about a
+        millisecond.  Returns the requests not yet retired."""
         n = C.c_int32()
         rc = lib().sr_server_pump(self._h, C.byref(n))
         if rc != SR_OK:

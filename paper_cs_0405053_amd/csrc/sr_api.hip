@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <ctime>
 #include <deque>
 #include <mutex>
 #include <cmath>
@@ -915,14 +916,36 @@ struct BatchStage {
   int cap;
 };
 
-// One persistent launch over the listed simulations (sr_batch_step).  `dev`
-// = nullptr: the launch's device memory is allocated here and freed after;
-// otherwise it is the caller's block of `dev_cap` bytes, nothing is
-// allocated, and a lattice whose buffers overflow ends the call with
-// SR_EOVERFLOW instead of being re-run with grown buffers.
-static int batch_core(sr_sim* const* sims, int32_t n, int32_t max_windows, hipStream_t stream,
-                      BatchStage& hs, void* dev, size_t dev_cap) {
-  const bool fixed_mem = dev != nullptr;
+// One persistent launch in flight: what batch_begin enqueued and batch_end
+// needs to collect it.
+struct BatchLaunch {
+  sr_sim* const* sims = nullptr;
+  int m = 0;                       // lattices in the launch (hs.idx[0..m))
+  int32_t max_windows = -1;
+  hipStream_t stream = nullptr;
+  char* base = nullptr;            // device block of the launch
+  bool owned = false;              // allocated by batch_begin (freed by batch_end)
+  LatRun* drun = nullptr;
+  BatchCounters* dctr = nullptr;
+  bool fixed_mem = false;
+};
+
+// Enqueue one persistent launch over the listed simulations (sr_batch_step)
+// on `stream` and return without waiting: run records and counters prepared,
+// queue cleared (the grid deals every lattice's first iteration itself), the
+// kernel bracketed by the first lattice's timing events.  `dev` = nullptr:
+// the launch's device memory is allocated here (and freed by batch_end);
+// otherwise it is the caller's block of `dev_cap` bytes and nothing is
+// allocated.  yield / notify: host-coherent words (or null), see BatchArgs.
+// *bl.m = 0 on return means no listed simulation had windows left.
+static int batch_begin(sr_sim* const* sims, int32_t n, int32_t max_windows, hipStream_t stream,
+                       BatchStage& hs, void* dev, size_t dev_cap, const uint32_t* yield, uint32_t* notify,
+                       BatchLaunch& bl) {
+  bl = BatchLaunch();
+  bl.sims = sims;
+  bl.max_windows = max_windows;
+  bl.stream = stream;
+  bl.fixed_mem = dev != nullptr;
   if (!sims || n <= 0) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "sr_batch_run needs simulations");
   if (n > 4096) SR_FAIL(sims[0], SR_EINVAL, "at most 4096 lattices per batch");
   int m = 0;
@@ -964,23 +987,26 @@ static int batch_core(sr_sim* const* sims, int32_t n, int32_t max_windows, hipSt
   // tickets its waves may hold ahead of production
   uint64_t qn = 1;
   while (qn < total / kShards + (uint64_t)m + (uint64_t)waves / kShards + 64) qn <<= 1;
-  const BatchLayout bl = batch_layout(m, qn);
+  const BatchLayout lay = batch_layout(m, qn);
   char* base = (char*)dev;
-  if (fixed_mem) {
-    if (bl.total > dev_cap)
+  if (bl.fixed_mem) {
+    if (lay.total > dev_cap)
       SR_FAIL(s0, SR_EINVAL, "this batch needs %zu bytes of launch memory, more than the %zu available "
-              "(fewer lattices or subdomains per call)", bl.total, dev_cap);
-  } else if (hipMalloc((void**)&base, bl.total) != hipSuccess) {
+              "(fewer lattices or subdomains per call)", lay.total, dev_cap);
+  } else if (hipMalloc((void**)&base, lay.total) != hipSuccess) {
     SR_FAIL(s0, SR_ENOMEM, "cannot allocate the batch queue");
   }
+  bl.base = base;
+  bl.owned = !bl.fixed_mem;
   auto release = [&]() {
-    if (!fixed_mem) (void)hipFree(base);
+    if (bl.owned) (void)hipFree(bl.base);
+    bl.owned = false;
   };
-  Lattice* dlat = (Lattice*)(base + bl.lat);
-  LatRun* drun = (LatRun*)(base + bl.run);
-  ShardRem* drem = (ShardRem*)(base + bl.rem);
-  BatchCounters* dctr = (BatchCounters*)(base + bl.ctr);
-  unsigned long long* dq = (unsigned long long*)(base + bl.q);
+  Lattice* dlat = (Lattice*)(base + lay.lat);
+  LatRun* drun = (LatRun*)(base + lay.run);
+  ShardRem* drem = (ShardRem*)(base + lay.rem);
+  BatchCounters* dctr = (BatchCounters*)(base + lay.ctr);
+  unsigned long long* dq = (unsigned long long*)(base + lay.q);
   for (int k = 0; k < m; ++k) {
     sr_sim* s = sims[hs.idx[k]];
     hs.lat[k] = s->L;
@@ -1007,22 +1033,50 @@ static int batch_core(sr_sim* const* sims, int32_t n, int32_t max_windows, hipSt
   BatchArgs args;
   args.ctr = dctr; args.q = dq; args.lat = dlat; args.run = drun; args.rem = drem;
   args.nlat = (uint32_t)m; args.qmask = (uint32_t)(qn - 1);
-  hipEvent_t e0 = s0->ev[0], e1 = s0->ev[1];
-  BatchCounters ctr;
-  if (launch_zero(base + bl.rem, bl.total - bl.rem, stream) != hipSuccess ||
+  args.yield = yield;
+  args.notify = notify;
+  if (launch_zero(base + lay.rem, lay.total - lay.rem, stream) != hipSuccess ||
       hipMemcpyAsync(dlat, hs.lat, m * sizeof(Lattice), hipMemcpyHostToDevice, stream) != hipSuccess ||
       hipMemcpyAsync(drun, hs.run, m * sizeof(LatRun), hipMemcpyHostToDevice, stream) != hipSuccess ||
-      hipEventRecord(e0, stream) != hipSuccess || launch_batch(args, shape, waves, lds, stream) != hipSuccess ||
-      hipEventRecord(e1, stream) != hipSuccess ||
-      hipMemcpyAsync(hs.run, drun, m * sizeof(LatRun), hipMemcpyDeviceToHost, stream) != hipSuccess ||
-      hipMemcpyAsync(&ctr, dctr, sizeof(ctr), hipMemcpyDeviceToHost, stream) != hipSuccess ||
-      hipStreamSynchronize(stream) != hipSuccess) {
+      hipEventRecord(s0->ev[0], stream) != hipSuccess || launch_batch(args, shape, waves, lds, stream) != hipSuccess ||
+      hipEventRecord(s0->ev[1], stream) != hipSuccess) {
+    (void)hipStreamSynchronize(stream);
     release();
-    SR_FAIL(s0, SR_EDEVICE, "persistent batch kernel failed: %s", hipGetErrorString(hipGetLastError()));
+    SR_FAIL(s0, SR_EDEVICE, "persistent batch launch failed: %s", hipGetErrorString(hipGetLastError()));
   }
+  bl.m = m;
+  bl.drun = drun;
+  bl.dctr = dctr;
+  return SR_OK;
+}
+
+// Has the launch ended (without waiting)?
+static bool batch_done(const BatchLaunch& bl, BatchStage& hs) {
+  if (bl.m == 0) return true;
+  return hipEventQuery(bl.sims[hs.idx[0]]->ev[1]) != hipErrorNotReady;
+}
+
+// Wait for the launch, read back the run records, bring every simulation's
+// host state up to date and release the launch memory.  Overflowed lattices
+// are re-run from their last committed window with grown buffers (or, for a
+// caller-provided block, reported as SR_EOVERFLOW since growing allocates).
+static int batch_end(BatchLaunch& bl, BatchStage& hs) {
+  if (bl.m == 0) return SR_OK;
+  sr_sim* const* sims = bl.sims;
+  const int m = bl.m;
+  sr_sim* s0 = sims[hs.idx[0]];
+  BatchCounters ctr;
+  const hipError_t we = hipEventSynchronize(s0->ev[1]);
+  const bool ok = we == hipSuccess &&
+      hipMemcpyAsync(hs.run, bl.drun, m * sizeof(LatRun), hipMemcpyDeviceToHost, bl.stream) == hipSuccess &&
+      hipMemcpyAsync(&ctr, bl.dctr, sizeof(ctr), hipMemcpyDeviceToHost, bl.stream) == hipSuccess &&
+      hipStreamSynchronize(bl.stream) == hipSuccess;
+  if (bl.owned) (void)hipFree(bl.base);
+  bl.owned = false;
+  bl.m = 0;
+  if (!ok) SR_FAIL(s0, SR_EDEVICE, "persistent batch kernel failed: %s", hipGetErrorString(hipGetLastError()));
   float ms = 0.f;
-  (void)hipEventElapsedTime(&ms, e0, e1);
-  release();
+  (void)hipEventElapsedTime(&ms, s0->ev[0], s0->ev[1]);
   int rc = SR_OK, first_bad = -1;
   for (int k = 0; k < m; ++k) {
     sr_sim* s = sims[hs.idx[k]];
@@ -1040,7 +1094,7 @@ static int batch_core(sr_sim* const* sims, int32_t n, int32_t max_windows, hipSt
     if (r.status == kOverflow) {
       // the decider leaves that iteration's flags in the lattice record
       uint32_t bits = (r.fl.ovf_hist ? 1u : 0u) | (r.fl.ovf_log ? 2u : 0u);
-      if (fixed_mem) {
+      if (bl.fixed_mem) {
         // growing the buffers would allocate: the window stays uncommitted
         one = SR_EOVERFLOW;
         s->err = "a boundary list or window log overflowed (growing it needs an allocation)";
@@ -1048,7 +1102,7 @@ static int batch_core(sr_sim* const* sims, int32_t n, int32_t max_windows, hipSt
         // grow what overflowed, then run this step's windows alone from the
         // last committed one
         one = grow(s, bits ? bits : 3u);
-        if (one == SR_OK) one = sr_run_window(s, max_windows > 0 ? max_windows : -1, nullptr, nullptr);
+        if (one == SR_OK) one = sr_run_window(s, bl.max_windows > 0 ? bl.max_windows : -1, nullptr, nullptr);
       }
     } else if (r.status == kNoConv) {
       one = SR_ENOCONV;
@@ -1070,6 +1124,16 @@ static int batch_core(sr_sim* const* sims, int32_t n, int32_t max_windows, hipSt
   }
   s0->last_batch_ms = ms;
   return rc;
+}
+
+// One synchronous persistent launch (sr_batch_step and its no-allocation
+// variant).
+static int batch_core(sr_sim* const* sims, int32_t n, int32_t max_windows, hipStream_t stream,
+                      BatchStage& hs, void* dev, size_t dev_cap) {
+  BatchLaunch bl;
+  int rc = batch_begin(sims, n, max_windows, stream, hs, dev, dev_cap, nullptr, nullptr, bl);
+  if (rc != SR_OK) return rc;
+  return batch_end(bl, hs);
 }
 
 extern "C" int sr_batch_step(sr_sim* const* sims, int32_t n, int32_t max_windows, void* stream_) {
@@ -1117,19 +1181,24 @@ extern "C" int sr_batch_step_static(sr_sim* const* sims, int32_t n, int32_t max_
 
 // ------------------------------------------------------------ serving
 // Continuous batching, driven by the caller.  sr_server_submit queues a
-// request; every sr_server_pump is one scheduling round: admit queued
-// requests in arrival order while their device footprint fits the HBM
-// budget, create their simulations, run one budgeted persistent batch step
-// over every admitted lattice (each commits at most `windows_per_round`
-// windows), and retire the lattices that reached their horizon, which frees
-// memory for the next round's admissions.  Requests submitted while a round
-// runs join at the next round.  A lattice's result does not depend on what it
-// shares a round with: the random streams are keyed by the request's own seed
-// and subdomains, and the block comes from the request alone.  All device
-// work happens inside sr_server_pump, on the caller's thread.
+// request.  One persistent launch at a time runs every admitted lattice
+// towards its horizon; it is left running between calls of sr_server_pump.
+// When a request is waiting whose footprint fits the budget, or a lattice
+// has reached its horizon, the pump raises a host-coherent yield word that
+// every lattice's decider reads at its next window boundary: each lattice
+// pauses there (committed time), the launch ends within about one window of
+// work, and the next pump retires the finished lattices, admits waiting
+// requests in arrival order while their device footprint fits, and starts
+// the next launch over all admitted lattices.  A request therefore waits for
+// the windows in flight, not for a round of fixed length.  A lattice's
+// result does not depend on what it shares a launch with: random streams are
+// keyed by the request's own seed and subdomains, the block comes from the
+// request alone, and pausing at a window boundary changes nothing (the
+// trajectory does not depend on the window).  All device work is on the
+// server's stream; the caller's thread does all host work.
 struct sr_server {
   size_t budget = 0, used = 0, peak_used = 0;
-  int32_t wpr = 8;
+  int32_t wpr = 0;                 // windows per lattice and launch (<= 0: no limit)
   hipStream_t stream = nullptr;
   struct Pending {
     uint64_t id;
@@ -1145,13 +1214,23 @@ struct sr_server {
     size_t bytes;
   };
   std::deque<Pending> pending;
-  std::vector<Active> active;
+  std::vector<Active> active;      // admitted, in the launch or waiting for the next
   std::deque<sr_result> done;
   uint64_t next_id = 1;
   std::chrono::steady_clock::time_point t0;
   int64_t rounds = 0, completed = 0, failed = 0, submitted = 0;
   int32_t peak_active = 0;
   double busy_s = 0.0;
+  // the launch in flight
+  bool running = false;
+  double t_launch = 0.0;
+  BatchLaunch bl;
+  std::vector<sr_sim*> launch_sims;
+  std::vector<Lattice> st_lat;
+  std::vector<LatRun> st_run;
+  std::vector<int> st_idx;
+  uint32_t* ctl = nullptr;         // pinned, host-coherent: [0] yield, [1] finished count
+  bool yield_raised = false;
 };
 
 static double server_now(const sr_server* v) {
@@ -1190,9 +1269,15 @@ extern "C" int sr_server_create(size_t hbm_budget, int32_t windows_per_round, vo
   if (!out || hbm_budget == 0) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "sr_server_create needs a budget");
   sr_server* v = new sr_server();
   v->budget = hbm_budget;
-  v->wpr = windows_per_round > 0 ? windows_per_round : 8;
+  v->wpr = windows_per_round;
   v->stream = (hipStream_t)hip_stream;
   v->t0 = std::chrono::steady_clock::now();
+  if (hipHostMalloc((void**)&v->ctl, 64, hipHostMallocCoherent) != hipSuccess) {
+    delete v;
+    SR_FAIL((sr_sim*)nullptr, SR_ENOMEM, "cannot allocate the server's control words");
+  }
+  v->ctl[0] = 0u;
+  v->ctl[1] = 0u;
   *out = v;
   return SR_OK;
 }
@@ -1222,8 +1307,47 @@ extern "C" int sr_server_submit(sr_server* v, const sr_params* pin, uint64_t* re
   return SR_OK;
 }
 
+// Collect the ended launch: run records back, finished lattices retired.
+static int server_collect(sr_server* v) {
+  BatchStage hs{v->st_lat.data(), v->st_run.data(), v->st_idx.data(), (int)v->st_idx.size()};
+  int rc = batch_end(v->bl, hs);
+  v->running = false;
+  v->busy_s += server_now(v) - v->t_launch;
+  std::vector<sr_server::Active> keep;
+  for (auto& a : v->active) {
+    if (a.s->failed != SR_OK) server_finish(v, a, a.s->failed);
+    else if (rc != SR_OK && rc != SR_ENOCONV) server_finish(v, a, rc);
+    else if (a.s->st.t_c >= a.s->H) server_finish(v, a, SR_OK);
+    else keep.push_back(a);
+  }
+  v->active.swap(keep);
+  return (rc == SR_OK || rc == SR_ENOCONV) ? SR_OK : rc;
+}
+
 extern "C" int sr_server_pump(sr_server* v, int32_t* n_open) {
   if (!v) return SR_EINVAL;
+  int rc = SR_OK;
+  if (v->running) {
+    BatchStage hs{v->st_lat.data(), v->st_run.data(), v->st_idx.data(), (int)v->st_idx.size()};
+    // wait a little for the launch to end, so that callers can spin on pump
+    for (int i = 0; i < 20 && !batch_done(v->bl, hs); ++i) {
+      if (!v->yield_raised) {
+        const bool arrived = !v->pending.empty() && v->used + v->pending.front().bytes <= v->budget;
+        const bool finished = __atomic_load_n(&v->ctl[1], __ATOMIC_ACQUIRE) != 0u;
+        if (arrived || finished) {
+          __atomic_store_n(&v->ctl[0], 1u, __ATOMIC_RELEASE);   // pause at the next window boundary
+          v->yield_raised = true;
+        }
+      }
+      struct timespec ts = {0, 50 * 1000};
+      nanosleep(&ts, nullptr);
+    }
+    if (!batch_done(v->bl, hs)) {
+      if (n_open) *n_open = (int32_t)(v->active.size() + v->pending.size());
+      return SR_OK;
+    }
+    rc = server_collect(v);
+  }
   while (!v->pending.empty() && v->used + v->pending.front().bytes <= v->budget) {
     sr_server::Pending q = std::move(v->pending.front());
     v->pending.pop_front();
@@ -1232,11 +1356,11 @@ extern "C" int sr_server_pump(sr_server* v, int32_t* n_open) {
     sr_params p = q.p;
     p.init_spins = q.spins.empty() ? nullptr : q.spins.data();
     sr_server::Active a{q.id, nullptr, q.t_arrive, server_now(v), q.bytes};
-    int rc = sr_create(&p, v->stream, &a.s);
-    if (rc != SR_OK) {
+    int c = sr_create(&p, v->stream, &a.s);
+    if (c != SR_OK) {
       sr_result r;
       std::memset(&r, 0, sizeof(r));
-      r.req_id = q.id; r.status = rc; r.t_arrive = q.t_arrive; r.t_start = a.t_start;
+      r.req_id = q.id; r.status = c; r.t_arrive = q.t_arrive; r.t_start = a.t_start;
       r.t_done = server_now(v);
       v->used -= q.bytes;
       v->failed++;
@@ -1245,26 +1369,31 @@ extern "C" int sr_server_pump(sr_server* v, int32_t* n_open) {
     }
     v->active.push_back(a);
   }
-  int rc = SR_OK;
-  if (!v->active.empty()) {
+  if (!v->active.empty() && rc == SR_OK) {
     v->peak_active = std::max<int32_t>(v->peak_active, (int32_t)v->active.size());
-    std::vector<sr_sim*> sims;
-    for (auto& a : v->active) sims.push_back(a.s);
-    double tb = server_now(v);
-    rc = sr_batch_step(sims.data(), (int32_t)sims.size(), v->wpr, v->stream);
-    v->busy_s += server_now(v) - tb;
-    v->rounds++;
-    std::vector<sr_server::Active> keep;
-    for (auto& a : v->active) {
-      if (a.s->failed != SR_OK) server_finish(v, a, a.s->failed);
-      else if (rc != SR_OK && rc != SR_ENOCONV) server_finish(v, a, rc);
-      else if (a.s->st.t_c >= a.s->H) server_finish(v, a, SR_OK);
-      else keep.push_back(a);
+    const size_t m = v->active.size();
+    v->launch_sims.resize(m);
+    for (size_t k = 0; k < m; ++k) v->launch_sims[k] = v->active[k].s;
+    v->st_lat.resize(m);
+    v->st_run.resize(m);
+    v->st_idx.resize(m);
+    BatchStage hs{v->st_lat.data(), v->st_run.data(), v->st_idx.data(), (int)m};
+    __atomic_store_n(&v->ctl[0], 0u, __ATOMIC_RELEASE);
+    __atomic_store_n(&v->ctl[1], 0u, __ATOMIC_RELEASE);
+    v->yield_raised = false;
+    v->t_launch = server_now(v);
+    rc = batch_begin(v->launch_sims.data(), (int32_t)m, v->wpr, v->stream, hs, nullptr, 0, v->ctl, v->ctl + 1,
+                     v->bl);
+    if (rc == SR_OK) {
+      v->rounds++;
+      v->running = v->bl.m > 0;
+    } else {
+      for (auto& a : v->active) server_finish(v, a, rc);
+      v->active.clear();
     }
-    v->active.swap(keep);
   }
   if (n_open) *n_open = (int32_t)(v->active.size() + v->pending.size());
-  return (rc == SR_OK || rc == SR_ENOCONV) ? SR_OK : rc;
+  return rc;
 }
 
 extern "C" int sr_server_poll(sr_server* v, sr_result* out, int32_t cap, int32_t* n) {
@@ -1296,6 +1425,14 @@ extern "C" int sr_server_stats(sr_server* v, sr_server_info* o) {
 
 extern "C" void sr_server_destroy(sr_server* v) {
   if (!v) return;
+  if (v->running) {
+    // end the launch at the next window boundaries, then collect it
+    __atomic_store_n(&v->ctl[0], 1u, __ATOMIC_RELEASE);
+    BatchStage hs{v->st_lat.data(), v->st_run.data(), v->st_idx.data(), (int)v->st_idx.size()};
+    (void)batch_end(v->bl, hs);
+    v->running = false;
+  }
   for (auto& a : v->active) sr_destroy(a.s);
+  if (v->ctl) (void)hipHostFree(v->ctl);
   delete v;
 }

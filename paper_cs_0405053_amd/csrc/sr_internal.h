@@ -222,6 +222,11 @@ struct BatchArgs {             // read-only for the kernel's lifetime
   LatRun* run;
   ShardRem* rem;               // [nlat][kShards]
   uint32_t nlat, qmask;
+  // host-coherent pinned words (or null): `yield` != 0 asks every lattice to
+  // pause at its next window boundary, so that the launch ends and the host
+  // can admit and retire; `notify` counts lattices that reached their horizon
+  const uint32_t* yield;
+  uint32_t* notify;
 };
 
 }  // namespace sr

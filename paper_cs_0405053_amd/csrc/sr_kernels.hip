@@ -790,10 +790,16 @@ __device__ void decide(const BatchArgs& B, int lat, int lane) {
       if (lane == 0) run->W = W;
     }
     if (st.t_c >= H) {
-      if (lane == 0) { run->status = kDone; run->st = st; }
+      if (lane == 0) {
+        run->status = kDone;
+        run->st = st;
+        if (B.notify) __hip_atomic_fetch_add(B.notify, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
       finish = true;
-    } else if (win_budget >= 0 && wins >= win_budget) {
-      // this launch's share of windows is done: pause at committed time
+    } else if ((win_budget >= 0 && wins >= win_budget) ||
+               (B.yield && __hip_atomic_load(B.yield, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0u)) {
+      // this launch's share of windows is done, or the host asked the launch
+      // to end: pause at committed time
       if (lane == 0) { run->status = kPaused; run->st = st; }
       finish = true;
     } else {

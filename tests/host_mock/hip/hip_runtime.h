@@ -13,7 +13,7 @@
 #define __align__(n) __attribute__((aligned(n)))
 #define HIP_SYMBOL(x) ((const void*)&(x))
 typedef int hipError_t;
-enum { hipSuccess = 0, hipErrorOutOfMemory = 2 };
+enum { hipSuccess = 0, hipErrorOutOfMemory = 2, hipErrorNotReady = 600 };
 typedef struct ihipStream_t* hipStream_t;
 typedef struct ihipEvent_t* hipEvent_t;
 typedef struct ihipGraph_t* hipGraph_t;
@@ -22,7 +22,7 @@ typedef struct ihipGraphNode_t* hipGraphNode_t;
 struct dim3 { unsigned x, y, z; dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {} };
 struct hipKernelNodeParams { void* func; dim3 gridDim, blockDim; unsigned sharedMemBytes; void** kernelParams; void** extra; };
 enum hipMemcpyKind { hipMemcpyHostToDevice, hipMemcpyDeviceToHost, hipMemcpyDeviceToDevice };
-enum { hipHostMallocDefault = 0 };
+enum { hipHostMallocDefault = 0, hipHostMallocCoherent = 0x40000000 };
 enum hipDeviceAttribute_t { hipDeviceAttributeMultiprocessorCount };
 hipError_t hipMalloc(void** p, size_t n);
 template <class T> hipError_t hipMalloc(T** p, size_t n) { return hipMalloc((void**)p, n); }
@@ -38,6 +38,8 @@ hipError_t hipEventCreate(hipEvent_t*);
 hipError_t hipEventDestroy(hipEvent_t);
 hipError_t hipEventRecord(hipEvent_t, hipStream_t);
 hipError_t hipEventElapsedTime(float*, hipEvent_t, hipEvent_t);
+hipError_t hipEventQuery(hipEvent_t);
+hipError_t hipEventSynchronize(hipEvent_t);
 const char* hipGetErrorString(hipError_t);
 hipError_t hipGetLastError();
 hipError_t hipGetDevice(int*);

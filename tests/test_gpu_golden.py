@@ -95,7 +95,7 @@ def test_serve256_results_equal_oracle():
     import paper_cs_0405053_amd as sr
     recs = _need("serve")
     reqs = W.serve_stream(n=256)
-    srv = sr.Server(hbm_budget=96 << 30, windows_per_round=8)
+    srv = sr.Server(hbm_budget=96 << 30)
     ids = {}
     for i, r in enumerate(reqs):
         p = {k: v for k, v in r.items() if k not in ("t_arrive", "req_id")}

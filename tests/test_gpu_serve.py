@@ -155,3 +155,27 @@ def test_tuned_run_reports_every_window():
     buf = (C.c_int32 * 4)()
     assert sr.lib().sr_run_window(s.handle, -1, buf, None) == sr.SR_EINVAL
     s.close()
+
+
+def test_arrival_joins_a_running_launch():
+    # a short request submitted while a long one is on the device starts at
+    # the long one's next window boundary and finishes long before it
+    sr = _sr()
+    long_p = W.params(512, 512, 0, 0, T=2.5, h=0.05, window=0.0, horizon=60.0, seed=4242, log_mode="digest")
+    short_p = W.params(64, 64, 0, 0, T=2.0, h=0.1, window=0.0, horizon=1.0, seed=4243, log_mode="digest")
+    srv = sr.Server(hbm_budget=8 << 30)
+    a = srv.submit(long_p)
+    srv.pump()                      # the long request's launch starts
+    time.sleep(0.05)
+    b = srv.submit(short_p)
+    got = drain(srv, 2)
+    st = srv.stats()
+    srv.close()
+    ra, rb = got[a], got[b]
+    say("long", ra["t_start"], ra["t_done"], "short", rb["t_arrive"], rb["t_start"], rb["t_done"], st)
+    assert ra["status"] == 0 and rb["status"] == 0
+    assert rb["t_done"] < ra["t_done"]              # joined, did not wait for the long one
+    assert st["rounds"] >= 2
+    for rid, p in ((a, long_p), (b, short_p)):
+        d, M, bond, flips = alone(sr, p)
+        assert (got[rid]["digest"], got[rid]["M"], got[rid]["bond_sum"], got[rid]["flips"]) == (d, M, bond, flips)
