@@ -634,6 +634,31 @@ __device__ __forceinline__ Step step_of(const RunView& v) {
 // others keep their lists: the slot array is copied forward and the change
 // masks cleared before anything is published.  Sets the per-shard counts
 // and shards_left before publishing any task.
+// Ordering between the tasks of one lattice.  A lattice spread over every
+// XCD shares its data through the eight L2s: a task publishes with an
+// agent-scope release, which writes the whole L2 back and which the L2
+// serialises (the costly half: with 6144 waves it took over half of the
+// batched form's time).  A lattice pinned to one XCD keeps all of its data in
+// that XCD's L2, which every CU of the XCD shares and which L1 writes through
+// to: publishing needs only the task's stores complete.  Every task starts
+// with the agent-scope acquire, which invalidates the CU's L1 (the
+// workgroup-scope L1 invalidate is not enough here: outside threadgroup-split
+// mode it left stale L1 lines visible to the next task, measured as wrong
+// trajectories).
+__device__ __forceinline__ void lattice_release(bool pinned) {
+  if (pinned) {
+    __asm__ volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+  } else {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  }
+}
+__device__ __forceinline__ void lattice_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
+// The XCD (XCC) this wave runs on: hardware register XCC_ID, bits 3:0.
+__device__ __forceinline__ int wave_xcc() {
+  return (int)__builtin_amdgcn_s_getreg((20) | (0 << 6) | (3 << 11)) & 15;
+}
+
 __device__ uint32_t enqueue_iteration(const BatchArgs& B, int lat, LatRun* run, CLattice& L, int it,
                                       int lane) {
   const int nsub = L.nsub;
@@ -646,15 +671,14 @@ __device__ uint32_t enqueue_iteration(const BatchArgs& B, int lat, LatRun* run, 
       const int left = nsub - w * 64;
       return left >= 64 ? ~0ull : ((1ull << left) - 1);
     }
+    // one 16-byte load at a time (fewer registers live in the decider)
     const uint4* p = reinterpret_cast<const uint4*>(nb + (size_t)w * 64);
-    uint4 x[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) x[k] = p[k];
     unsigned long long m = 0;
-#pragma unroll
+#pragma unroll 1
     for (int k = 0; k < 4; ++k) {
-      const unsigned long long lo = ((unsigned long long)x[k].y << 32) | x[k].x;
-      const unsigned long long hi = ((unsigned long long)x[k].w << 32) | x[k].z;
+      const uint4 x = p[k];
+      const unsigned long long lo = ((unsigned long long)x.y << 32) | x.x;
+      const unsigned long long hi = ((unsigned long long)x.w << 32) | x.z;
       m |= (((lo & 0x0101010101010101ull) * 0x0102040810204080ull) >> 56) << (16 * k);
       m |= (((hi & 0x0101010101010101ull) * 0x0102040810204080ull) >> 56) << (16 * k + 8);
     }
@@ -685,17 +709,22 @@ __device__ uint32_t enqueue_iteration(const BatchArgs& B, int lat, LatRun* run, 
   }
   count = (uint32_t)wave_sum64(count);
   if (count == 0) return 0;                     // caller turns this into an error
-  // task i of the iteration goes to shard (off + i) % kShards, the
-  // (i / kShards)-th of that shard; lane s < kShards handles shard s
+  // spread lattice: task i of the iteration goes to shard (off + i) %
+  // kShards, the (i / kShards)-th of that shard; pinned lattice: every task
+  // to its XCD's shard, the i-th of it.  Lane s < kShards handles shard s.
+  const int xcd = L.xcd;
+  const bool pinned = xcd >= 0;
   const int off = lat % kShards;
   const int ls = (lane - off + kShards) % kShards;         // first task index of shard `lane`
-  const uint32_t ns = lane < kShards ? (count > (uint32_t)ls ? (count - 1 - ls) / kShards + 1 : 0u) : 0u;
+  const uint32_t ns = lane < kShards ? (pinned ? (lane == xcd ? count : 0u)
+                                               : (count > (uint32_t)ls ? (count - 1 - ls) / kShards + 1 : 0u))
+                                     : 0u;
   if (lane < kShards) B.rem[(size_t)lat * kShards + lane].n = (int32_t)ns;
   if (lane == 0) {
-    run->shards_left = (int32_t)(count < (uint32_t)kShards ? count : (uint32_t)kShards);
+    run->shards_left = pinned ? 1 : (int32_t)(count < (uint32_t)kShards ? count : (uint32_t)kShards);
     run->tasks += count;
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  lattice_release(pinned);
   unsigned long long sbase = 0;
   if (lane < kShards && ns) sbase = atomicAdd(&B.ctr->sh[lane].tail, (unsigned long long)ns);
   unsigned long long bases[kShards];           // wave-uniform, read before the divergent walk
@@ -704,15 +733,16 @@ __device__ uint32_t enqueue_iteration(const BatchArgs& B, int lat, LatRun* run, 
   const size_t qn = (size_t)B.qmask + 1;
   if (it == 0) {
     // every subdomain runs: task i is subdomain i, in shard (off + i) mod
-    // kShards at position i / kShards; 64 is a multiple of kShards, so a
-    // lane's shard is the same in every round
-    const int sh = (off + lane) % kShards;
+    // kShards at position i / kShards (pinned: in its XCD's shard at
+    // position i); 64 is a multiple of kShards, so a lane's shard is the same
+    // in every round
+    const int sh = pinned ? xcd : (off + lane) % kShards;
     unsigned long long base = bases[0];
 #pragma unroll
     for (int k = 1; k < kShards; ++k) base = sh == k ? bases[k] : base;
     unsigned long long* qs = B.q + (size_t)sh * qn;
     for (int d = lane; d < nsub; d += 64) {
-      const unsigned long long at = base + (unsigned)d / kShards;
+      const unsigned long long at = base + (pinned ? (unsigned)d : (unsigned)d / kShards);
       __hip_atomic_store(&qs[at & B.qmask], ((at + 1) << 32) | ((unsigned long long)lat << 20) | (unsigned)d,
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -730,11 +760,11 @@ __device__ uint32_t enqueue_iteration(const BatchArgs& B, int lat, LatRun* run, 
       const int bit = ctz64(m);
       m &= m - 1;
       const int d = (w0 + lane) * 64 + bit;
-      const int sh = (int)((off + i) % kShards);
+      const int sh = pinned ? xcd : (int)((off + i) % kShards);
       unsigned long long base = bases[0];
 #pragma unroll
       for (int k = 1; k < kShards; ++k) base = sh == k ? bases[k] : base;
-      const unsigned long long at = base + i / kShards;
+      const unsigned long long at = base + (pinned ? i : i / kShards);
       const unsigned long long v = ((at + 1) << 32) | ((unsigned long long)lat << 20) | (unsigned)d;
       __hip_atomic_store(&B.q[(size_t)sh * qn + (at & B.qmask)], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       i++;
@@ -748,9 +778,10 @@ __device__ uint32_t enqueue_iteration(const BatchArgs& B, int lat, LatRun* run, 
 // Sec. 4 box for the whole lattice, then the next iteration, the next
 // window (committed time advances), or completion.
 __device__ void decide(const BatchArgs& B, int lat, int lane) {
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  LatRun* run = &B.run[lat];
   CLattice& L = ((CLattice*)B.lat)[lat];
+  const bool pinned = L.xcd >= 0;
+  lattice_acquire();
+  LatRun* run = &B.run[lat];
   const RunView rv = load_run(run, lane);
   IterFlags f;
   f.changed = rv.u32(offsetof(LatRun, fl) + offsetof(IterFlags, changed));
@@ -808,7 +839,7 @@ __device__ void decide(const BatchArgs& B, int lat, int lane) {
     }
   }
   if (finish) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    lattice_release(pinned);
     if (lane == 0) atomicAdd(&B.ctr->done, 1u);
     return;
   }
@@ -821,7 +852,7 @@ __device__ void decide(const BatchArgs& B, int lat, int lane) {
   if (enqueue_iteration(B, lat, run, L, next_it, lane) == 0) {
     // a changed iteration must schedule some subdomain; never wait forever
     if (lane == 0) run->status = kBad;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    lattice_release(pinned);
     if (lane == 0) atomicAdd(&B.ctr->done, 1u);
   }
 }
@@ -834,14 +865,16 @@ __device__ void decide(const BatchArgs& B, int lat, int lane) {
 constexpr uint32_t kSpinBudget = 20u << 20;
 constexpr uint32_t kProgressEvery = 4096;
 
-// Wave w serves shard w % kShards (consecutive workgroups go to different
-// XCDs, so each shard's counters are hit mostly from one XCD).  Per task:
-// wait for the slot of the ticket held, acquire, relax, release, count the
-// task down while taking the next ticket.  A held ticket whose task is not
-// produced yet blocks no one: tasks are produced by deciders, and a wave
-// finishes its current task before it waits.  Registers are capped so that
-// six waves share a SIMD (80 VGPRs and a few spills instead of 105, i.e. four
-// waves): more waves hide more of each task's latency chain.
+// Shard g is the queue of XCD g: a wave serves the shard of the XCD it runs
+// on (its XCC_ID register; without pinning, workgroup w % kShards, which the
+// dispatcher places on XCD w % kShards), so a pinned lattice's tasks and its
+// decider all run on its XCD.  Per task: wait for the slot of the ticket held,
+// acquire, relax, release, count the task down while taking the next ticket.
+// A held ticket whose task is not produced yet blocks no one: tasks are
+// produced by deciders, and a wave finishes its current task before it waits.
+// Registers are capped so that six waves share a SIMD (80 VGPRs and a few
+// spills instead of 105, i.e. four waves): more waves hide more of each
+// task's latency chain.
 // BX, BY, NW as for the plain kernels: <16, 16, true> (constant index
 // arithmetic, no wrap handling) for launches of large lattices that all have
 // 16x16 blocks and two or more subdomains per direction, <0, 0, false>
@@ -851,13 +884,27 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   extern __shared__ int8_t tile[];
   const int lane = lane_id();
   CLattice* lats = (CLattice*)B.lat;
-  const int g = (int)(blockIdx.x % kShards);
+  // the wave serves the shard of the XCD it runs on (pinned lattices keep
+  // all their tasks there); without pinning, the shard of its workgroup id
+  const int g = B.pinned_xcc ? (wave_xcc() & (kShards - 1)) : (int)(blockIdx.x % kShards);
   ShardCtr* sc = &B.ctr->sh[g];
   const unsigned long long* qg = B.q + (size_t)g * ((size_t)B.qmask + 1);
-  // the first iteration of every lattice (all its subdomains) is dealt by
-  // the grid before any wave takes a ticket; tasks are taken as they appear
-  for (int k = blockIdx.x; k < (int)B.nlat; k += gridDim.x)
-    enqueue_iteration(B, k, &B.run[k], lats[k], 0, lane);
+  // the first iteration of every lattice (all its subdomains) is dealt
+  // before the wave takes a ticket: this XCD's pinned lattices, then spread
+  // ones, each handed out once; tasks are taken as they appear
+  for (int part = 0; part < 2; ++part) {
+    const int x = part == 0 ? g : kShards;
+    if (part == 0 && !B.pinned_xcc) continue;
+    const int lo = B.seed_off[x], n = (x == kShards ? (int)B.nlat : B.seed_off[x + 1]) - lo;
+    for (;;) {
+      uint32_t i = 0;
+      if (lane == 0) i = atomicAdd(&B.seed_next[x], 1u);
+      i = rdl(i, 0);
+      if ((int)i >= n) break;
+      const int k = B.seed_list[lo + (int)i];
+      enqueue_iteration(B, k, &B.run[k], lats[k], 0, lane);
+    }
+  }
   unsigned long long t = 0;
   if (lane == 0) t = atomicAdd(&sc->head, 1ull);
   t = ((uint64_t)rdl((uint32_t)(t >> 32), 0) << 32) | rdl((uint32_t)t, 0);
@@ -891,7 +938,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     const uint32_t pay = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
     const int lat = (int)((pay >> 20) & 0xFFF);
     const int d = (int)(pay & 0xFFFFF);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const bool pinned = lats[lat].xcd >= 0;
+    lattice_acquire();
     LatRun* run = &B.run[lat];
     const Step st = step_of(load_run(run, lane));
     relax_subdomain<BX, BY, NW>(lats[lat], st, d, tile, &run->fl);
@@ -901,7 +949,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     // time).  A convergent no-op on either side keeps one release, executed
     // by the whole wave.
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    lattice_release(pinned);
     __builtin_amdgcn_wave_barrier();
     // count this task down and take the next ticket: both memory-side
     // atomics are in flight together
@@ -1025,11 +1073,24 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t stream) {
   return hipGetLastError();
 }
 
-// The compile-time 16x16 body needs 121 VGPRs inside the task loop: capped at
-// four waves per SIMD it runs without spills (at six it spills 124 B per
-// lane and is slower).  The runtime-shape kernel keeps six waves.
+// The compile-time 16x16 body needs 116 VGPRs inside the task loop: capped at
+// four waves per SIMD it runs without spills.  Measured on the 512-lattice
+// batch and three 1024x1024 lattices (flips/s): runtime shape at 6 / 7 / 8
+// waves per SIMD 8.20e7 / 8.19e7 / 7.68e7 and 5.74e7 / 5.51e7 / 5.25e7
+// (more waves, more spills); 16x16 at 4 / 5 / 6 waves 8.10e7 / 8.22e7 /
+// 7.87e7 and 6.31e7 / 6.17e7 / 6.15e7.
 static const void* batch_kernel_for(int shape) {
   return shape == kBatch16NoWrap ? (const void*)batch_kernel<16, 16, true, 4> : (const void*)batch_kernel<0, 0, false, 6>;
+}
+
+// Each workgroup records the XCD (XCC_ID) it ran on.
+__global__ void xcc_probe_kernel(uint32_t* out, int n) {
+  if (threadIdx.x == 0 && (int)blockIdx.x < n) out[blockIdx.x] = (uint32_t)wave_xcc();
+}
+
+hipError_t launch_xcc_probe(uint32_t* out, int n, hipStream_t stream) {
+  hipLaunchKernelGGL(xcc_probe_kernel, dim3((unsigned)n), dim3(64), 0, stream, out, n);
+  return hipGetLastError();
 }
 
 hipError_t launch_batch(const BatchArgs& B, int shape, int waves, size_t lds, hipStream_t stream) {
