@@ -1054,11 +1054,11 @@ static int batch_begin(sr_sim* const* sims, int32_t n, int32_t max_windows, hipS
   int dev_id = 0, ncu = 0;
   HIP_OR_FAIL(s0, hipGetDevice(&dev_id));
   HIP_OR_FAIL(s0, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev_id));
-  // the compile-time 16x16 body pays off on large lattices (measured: three
-  // 1024x1024 lattices 5.8e7 -> 6.3e7 flips/s); on many small ones the
-  // runtime-shape kernel with more waves per SIMD is faster (512 lattices of
-  // 32..512: 8.3e7 vs 8.1e7)
-  int shape = (all16 && total >= 1024 * (uint64_t)m) ? kBatch16NoWrap : kBatchGeneric;
+  // the compile-time 16x16 body whenever every lattice can take it
+  // (measured with six waves per SIMD: 512 lattices of 32..512, 2.93 s
+  // against 3.07-3.26 s for the runtime-shape body; three 1024x1024
+  // lattices, 1.05 s against 1.18 s)
+  int shape = all16 ? kBatch16NoWrap : kBatchGeneric;
   if (const char* k = std::getenv("SR_BATCH_KERNEL")) {     // test knob: force one kernel
     if (!std::strcmp(k, "generic")) shape = kBatchGeneric;
     else if (!std::strcmp(k, "16x16") && all16) shape = kBatch16NoWrap;

@@ -60,7 +60,21 @@ constexpr int lane_shift(int nblk) {
 // index arithmetic); 0: read from the lattice.  NW: the lattice has at least
 // two subdomains in each direction, so no block wraps onto itself (the wrap
 // selects on neighbour indices and edge pushes drop out at compile time).
-template <int BX, int BY, bool NW = false, class LT>
+// A store of a run's results.  COH: device-coherent (written through to the
+// point where every XCD's reads meet, so the task publishes by waiting for
+// its stores, with no L2 write-back); else an ordinary store (the plain
+// kernels publish at the kernel boundary).
+template <bool COH, class T, class U>
+__device__ __forceinline__ void gput(T* p, U v) {
+  if constexpr (COH) {
+    __hip_atomic_store(p, (T)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    *p = (T)v;
+  }
+}
+
+// COH: every store of the run's results is device-coherent (see gput).
+template <int BX, int BY, bool NW = false, bool COH = false, class LT>
 __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int d,
                                                 int8_t* lds, IterFlags* fl) {
   static_assert((BX == 0) == (BY == 0), "both or neither block sides fixed");
@@ -281,7 +295,7 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
     int at = nev - k + lane;
     uint64_t dsum = 0;
     if (lane < k) {
-      if (at < wcap) wl[at] = lbuf;
+      if (at < wcap) gput<COH>(&wl[at], lbuf);
       int v = (int)(lbuf & 0xFFFF);
       int ly = v / bx, lx = v - ly * bx;
       int64_t g = (int64_t)(y0 + ly) * L.Lx + x0 + lx;
@@ -317,7 +331,7 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
     if (since >= L.ckint && ckc < L.nck && tn > last_t) {
       // state after every item with tick < tn: a place to resume from
       Ckpt* c = ckbase + ckc;
-      c->cls[lane] = cls;
+      gput<COH>(&c->cls[lane], cls);
       // metadata word `lane` (dsum: the log entries flushed so far)
       const uint32_t clo = (uint32_t)__shfl((int)ncnt, (2 * lane) & 63, 64);
       const uint32_t chi = (uint32_t)__shfl((int)ncnt, (2 * lane + 1) & 63, 64);
@@ -335,7 +349,7 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
       w = lane == kCkOut01 ? ((uint64_t)(uint32_t)nN | ((uint64_t)(uint32_t)nS << 32)) : w;
       w = lane == kCkOut23 ? ((uint64_t)(uint32_t)nW | ((uint64_t)(uint32_t)nE << 32)) : w;
       w = lane == kCkHead ? (uint64_t)(uint32_t)in.head : w;
-      if (lane < 32) c->meta[lane] = lane < kCkWords ? w : 0ull;
+      if (lane < 32) gput<COH>(&c->meta[lane], lane < kCkWords ? w : 0ull);
       ckc++;
       since = 0;
     }
@@ -466,7 +480,7 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
     const int v = lane + 64 * i;
     if (v < nblk) {
       const int ly = v / bx, lx = v - ly * bx;
-      so[(int64_t)(y0 + ly) * L.Lx + x0 + lx] = ((cls >> (4 * i)) & 15) < 5 ? (int8_t)1 : (int8_t)-1;
+      gput<COH>(&so[(int64_t)(y0 + ly) * L.Lx + x0 + lx], ((cls >> (4 * i)) & 15) < 5 ? (int8_t)1 : (int8_t)-1);
     }
   }
   // compare step (c): own lists against the previous iteration's, then the
@@ -479,7 +493,7 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
     const uint64_t* cur = lcur + e * hcap;
     fc[e] = first ? (n > 0 ? (int64_t)(cur[0] >> kPosBits) : kTickInf)
                   : first_change(cur, n, lprev + e * hcap, np[e], n0[e], lane);
-    for (int i = lane; i < n; i += 64) ob[e * hcap + i] = cur[i];
+    for (int i = lane; i < n; i += 64) gput<COH>(&ob[e * hcap + i], cur[i]);
   }
   uint32_t* cnt_out = hcnt_at(L, sout) + d * kEdges;
   int64_t* fct_out = fct_at(L, sout) + d * kEdges;
@@ -487,40 +501,40 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
     uint32_t emask = 0;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      cnt_out[e] = (uint32_t)nn[e];
-      fct_out[e] = fc[e];
+      gput<COH>(&cnt_out[e], (uint32_t)nn[e]);
+      gput<COH>(&fct_out[e], fc[e]);
       emask |= fc[e] != kTickInf ? 1u << e : 0u;
     }
     Carry* co = &carry_at(L, st.wp ^ 1)[d];
-    co->j = j; co->anchor = anchor; co->acc = acc;
-    co->digest = dig_in + dtot;
-    co->flips = flips_in + nev;
-    co->wflips = nev;
-    co->nbound = nbound;
-    co->nbmax = nbound > nbmax_in ? nbound : nbmax_in;
-    L.stat[d].events = ev_in + (unsigned long long)(nev - nev0);
-    L.stat[d].runs = runs_in + 1ull;
-    L.wcnt[d] = (uint32_t)nev;
-    L.ckn[d] = (uint32_t)ckc;
-    slot_at(L, st.it & 1)[d] = (uint8_t)sout;
-    chg_at(L, st.it & 1)[d] = (uint8_t)emask;
+    gput<COH>(&co->j, j); gput<COH>(&co->anchor, anchor); gput<COH>(&co->acc, acc);
+    gput<COH>(&co->digest, dig_in + dtot);
+    gput<COH>(&co->flips, flips_in + nev);
+    gput<COH>(&co->wflips, nev);
+    gput<COH>(&co->nbound, nbound);
+    gput<COH>(&co->nbmax, nbound > nbmax_in ? nbound : nbmax_in);
+    gput<COH>(&L.stat[d].events, ev_in + (unsigned long long)(nev - nev0));
+    gput<COH>(&L.stat[d].runs, runs_in + 1ull);
+    gput<COH>(&L.wcnt[d], (uint32_t)nev);
+    gput<COH>(&L.ckn[d], (uint32_t)ckc);
+    gput<COH>(&slot_at(L, st.it & 1)[d], (uint8_t)sout);
+    gput<COH>(&chg_at(L, st.it & 1)[d], (uint8_t)emask);
     uint32_t ovf = ((nN > hcap || nS > hcap || nW > hcap || nE > hcap) ? 1u : 0u) |
                    ((nev > wcap || runaway) ? 2u : 0u);
-    if (emask) fl->changed = 1u;
+    if (emask) gput<COH>(&fl->changed, 1u);
     if (L.need) {
       // batched form: this run consumed its own "runs now" mark; the
       // neighbour facing each changed edge runs in the next iteration
       // (plain byte stores of 0 / 1: one subdomain per byte, and the
       // fences of the batched form order them)
-      need_at(L, st.it & 1)[d] = 0;
+      gput<COH>(&need_at(L, st.it & 1)[d], (uint8_t)0);
       uint8_t* nb = need_at(L, (st.it + 1) & 1);
       const int facing[4] = {dn, ds, dw, de};
 #pragma unroll
       for (int e = 0; e < 4; ++e)
-        if (emask & (1u << e)) nb[facing[e]] = 1;
+        if (emask & (1u << e)) gput<COH>(&nb[facing[e]], (uint8_t)1);
     }
-    if (ovf & 1u) fl->ovf_hist = 1u;
-    if (ovf & 2u) fl->ovf_log = 1u;
+    if (ovf & 1u) gput<COH>(&fl->ovf_hist, 1u);
+    if (ovf & 2u) gput<COH>(&fl->ovf_log, 1u);
   }
 }
 
@@ -634,20 +648,22 @@ __device__ __forceinline__ Step step_of(const RunView& v) {
 // others keep their lists: the slot array is copied forward and the change
 // masks cleared before anything is published.  Sets the per-shard counts
 // and shards_left before publishing any task.
-// Ordering between the tasks of one lattice.  A lattice spread over every
-// XCD shares its data through the eight L2s: a task publishes with an
-// agent-scope release, which writes the whole L2 back and which the L2
-// serialises (the costly half: with 6144 waves it took over half of the
-// batched form's time).  A lattice pinned to one XCD keeps all of its data in
-// that XCD's L2, which every CU of the XCD shares and which L1 writes through
-// to: publishing needs only the task's stores complete.  Every task starts
-// with the agent-scope acquire, which invalidates the CU's L1 (the
-// workgroup-scope L1 invalidate is not enough here: outside threadgroup-split
-// mode it left stale L1 lines visible to the next task, measured as wrong
-// trajectories).
+// Ordering between the tasks of one lattice.  A task's results are written
+// with device-coherent stores (through to the point where all XCDs' reads
+// meet), so a task publishes by waiting for its stores; it starts with the
+// device-scope acquire, which invalidates this CU's L1 and the L2's copies of
+// other XCDs' data (the workgroup-scope L1 invalidate is not enough: outside
+// threadgroup-split mode it left stale L1 lines visible to the next task,
+// measured as wrong trajectories).  The decider writes with ordinary stores:
+// for a lattice spread over every XCD it publishes with the device-scope
+// release, which writes the whole L2 back and which the L2 serialises (once
+// per task it took over half of the batched form's time); a lattice pinned to
+// one XCD keeps all its data in that XCD's L2, which every CU of the XCD
+// shares and which L1 writes through to, so there too a wait suffices.
+__device__ __forceinline__ void task_release() { __asm__ volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory"); }
 __device__ __forceinline__ void lattice_release(bool pinned) {
   if (pinned) {
-    __asm__ volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+    task_release();
   } else {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   }
@@ -872,13 +888,13 @@ constexpr uint32_t kProgressEvery = 4096;
 // acquire, relax, release, count the task down while taking the next ticket.
 // A held ticket whose task is not produced yet blocks no one: tasks are
 // produced by deciders, and a wave finishes its current task before it waits.
-// Registers are capped so that six waves share a SIMD (80 VGPRs and a few
-// spills instead of 105, i.e. four waves): more waves hide more of each
-// task's latency chain.
+// Registers are capped so that six waves share a SIMD (80 VGPRs; the few
+// spills are reloaded once per task, never in the event loop): more waves
+// hide more of each task's latency chain.
 // BX, BY, NW as for the plain kernels: <16, 16, true> (constant index
-// arithmetic, no wrap handling) for launches of large lattices that all have
-// 16x16 blocks and two or more subdomains per direction, <0, 0, false>
-// otherwise; WPE caps the waves per SIMD (registers per wave).
+// arithmetic, no wrap handling) for launches whose lattices all have 16x16
+// blocks and two or more subdomains per direction, <0, 0, false> otherwise;
+// WPE caps the waves per SIMD (registers per wave).
 template <int BX, int BY, bool NW, int WPE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void batch_kernel(BatchArgs B) {
   extern __shared__ int8_t tile[];
@@ -938,18 +954,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     const uint32_t pay = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
     const int lat = (int)((pay >> 20) & 0xFFF);
     const int d = (int)(pay & 0xFFFFF);
-    const bool pinned = lats[lat].xcd >= 0;
     lattice_acquire();
     LatRun* run = &B.run[lat];
     const Step st = step_of(load_run(run, lane));
-    relax_subdomain<BX, BY, NW>(lats[lat], st, d, tile, &run->fl);
-    // The run ends, and the count below starts, with a lane-0 region; left
-    // alone the compiler merges the two and duplicates the release into both
-    // paths, i.e. two L2 write-backs per task (40% of the batched form's
-    // time).  A convergent no-op on either side keeps one release, executed
-    // by the whole wave.
+    relax_subdomain<BX, BY, NW, true>(lats[lat], st, d, tile, &run->fl);
+    // the run's stores are device-coherent: publishing waits for them only
+    // (convergent no-ops around it keep one wait, executed by the whole wave,
+    // instead of one in each lane-0 region the compiler would merge it into)
     __builtin_amdgcn_wave_barrier();
-    lattice_release(pinned);
+    task_release();
     __builtin_amdgcn_wave_barrier();
     // count this task down and take the next ticket: both memory-side
     // atomics are in flight together
@@ -1080,7 +1093,7 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t stream) {
 // (more waves, more spills); 16x16 at 4 / 5 / 6 waves 8.10e7 / 8.22e7 /
 // 7.87e7 and 6.31e7 / 6.17e7 / 6.15e7.
 static const void* batch_kernel_for(int shape) {
-  return shape == kBatch16NoWrap ? (const void*)batch_kernel<16, 16, true, 4> : (const void*)batch_kernel<0, 0, false, 6>;
+  return shape == kBatch16NoWrap ? (const void*)batch_kernel<16, 16, true, 6> : (const void*)batch_kernel<0, 0, false, 6>;
 }
 
 // Each workgroup records the XCD (XCC_ID) it ran on.
