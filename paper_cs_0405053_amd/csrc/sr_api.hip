@@ -949,13 +949,18 @@ static bool xcc_pinning_usable(int dev, void* scratch, hipStream_t stream) {
 }
 
 // Placement of a launch's lattices on XCDs.  A lattice no larger than an
-// XCD's fair share of the launch's subdomains runs all its tasks on one XCD
-// (its data then stays in that XCD's L2 and its tasks synchronise without
-// whole-L2 fences); larger ones are spread over all XCDs.  Pinned lattices go
-// heaviest first to the least-loaded XCD, the weight being subdomains x
-// remaining time x the mean class rate.  Fills L.xcd, the seed lists and the
-// largest number of tasks one shard can hold at once.
-static uint64_t place_lattices(sr_sim* const* sims, BatchStage& hs, int m, bool pin, uint64_t total) {
+// XCD's fair share of the launch's subdomains, and whose iteration one XCD's
+// waves run at once (at most twice as many subdomains as waves per XCD),
+// runs all its tasks on one XCD: its data then stays in that XCD's L2 and
+// its deciders publish without a whole-L2 write-back.  Larger ones are
+// spread over all XCDs (pinned, their windows would take several times
+// longer, and a launch that must end at the next window boundaries waits
+// for the slowest).  Pinned lattices go heaviest first to the least-loaded
+// XCD, the weight being subdomains x remaining time x the mean class rate.
+// Fills L.xcd, the seed lists and the largest number of tasks one shard can
+// hold at once.
+static uint64_t place_lattices(sr_sim* const* sims, BatchStage& hs, int m, bool pin, uint64_t total,
+                               int waves) {
   int32_t* list = hs.seed;
   int32_t* off = hs.seed + m;
   std::vector<int> pinned, spread;
@@ -968,7 +973,7 @@ static uint64_t place_lattices(sr_sim* const* sims, BatchStage& hs, int m, bool 
     const int ncls = s->L.Lz > 1 ? kClasses3 : kClasses;
     for (int c = 0; c < ncls; ++c) rsum += (double)s->L.rate[c];
     w[k] = (double)s->L.nsub * (double)std::max<int64_t>(s->H - s->st.t_c, 1) * (rsum / ncls + 1.0);
-    const bool fits = pin && (uint64_t)s->L.nsub * kShards <= total;
+    const bool fits = pin && (uint64_t)s->L.nsub * kShards <= total && s->L.nsub <= 2 * (waves / kShards);
     (fits ? pinned : spread).push_back(k);
     hs.lat[k].xcd = -1;
   }
@@ -1082,7 +1087,7 @@ static int batch_begin(sr_sim* const* sims, int32_t n, int32_t max_windows, hipS
     SR_FAIL(s0, SR_ENOMEM, "cannot allocate the batch queue");
   }
   const bool pin = xcc_pinning_usable(dev_id, base, stream);
-  const uint64_t most = place_lattices(sims, hs, m, pin, total);
+  const uint64_t most = place_lattices(sims, hs, m, pin, total, waves);
   uint64_t qn2 = 1;
   while (qn2 < most + (uint64_t)m + (uint64_t)waves + 64) qn2 <<= 1;
   qn = qn2;
