@@ -163,7 +163,9 @@ int sr_run_window(sr_sim* s, int32_t n_windows, int32_t* iters_out, int32_t* n_d
 int sr_observables(sr_sim* s, sr_obs* out);
 
 /* Return to time 0: initial spins again (random, all up, or the spins given
- * at creation), empty carry, counters cleared; keeps every allocation. */
+ * at creation), empty carry, counters cleared, and an adapted step size back
+ * to the one chosen at creation (or at load), so that a reset simulation
+ * repeats the same windows; keeps every allocation. */
 int sr_reset(sr_sim* s);
 
 /* Release everything.  NULL-safe. */

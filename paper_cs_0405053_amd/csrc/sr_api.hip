@@ -36,7 +36,6 @@ hipError_t launch_observables3d(const int8_t* s, int Lx, int Ly, int Lz, unsigne
                                 hipStream_t stream);
 hipError_t launch_batch(const BatchArgs& B, int shape, int waves, size_t lds, hipStream_t stream);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t stream);
-hipError_t launch_xcc_probe(uint32_t* out, int n, hipStream_t stream);
 const void* clear_flags_kernel_ptr();
 const void* relax_graph_kernel_ptr(const Lattice& L);
 int batch_waves_per_cu(int shape, size_t lds);
@@ -51,6 +50,7 @@ struct sr_sim {
   Step st;
   hipStream_t stream = nullptr;
   int64_t W = 0, H = 0;             // window and horizon in ticks
+  int64_t W0 = 0;                   // window at creation (or load): reset returns to it
   bool tune = false;                // window chosen by the tuner: adapt it
   int64_t Wmin = 1, Wmax = 1;       // bounds of the adapted window
   int64_t windows = 0, iterations = 0;
@@ -370,7 +370,7 @@ static int create_impl(const sr_params* pin, void* stream, sr_sim** out, bool in
   s->p = p;
   s->p.init_spins = nullptr;
   s->stream = (hipStream_t)stream;
-  s->W = W; s->H = H;
+  s->W = W; s->W0 = W; s->H = H;
   s->tune = tuned_window;
   s->Wmin = std::max<int64_t>(1, to_ticks(1.0 / 64.0, p.tick_bits));
   s->Wmax = std::max<int64_t>(s->Wmin, to_ticks(4.0, p.tick_bits));
@@ -383,7 +383,6 @@ static int create_impl(const sr_params* pin, void* stream, sr_sim** out, bool in
   L.S = 1 << L.sshift;
   L.tick_bits = p.tick_bits;
   L.wipe = p.step_rule == SR_STEP_WIPE ? 1 : 0;
-  L.xcd = -1;
   if (rate_table(p.J, p.h, p.T, p.rule, is3d(p) ? 6 : 4, L.rate) != 0) { delete s; SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "bad rate parameters"); }
   L.seed_lo = (uint32_t)p.seed; L.seed_hi = (uint32_t)(p.seed >> 32);
   if (s->tune) s->Wmax = std::max(s->Wmin, std::min(s->Wmax, 4 * W));
@@ -708,6 +707,7 @@ extern "C" int sr_reset(sr_sim* s) {
   HIP_OR_FAIL(s, hipMemsetAsync(L.stat, 0, (size_t)L.nsub * sizeof(SubStat), s->stream));
   HIP_OR_FAIL(s, hipStreamSynchronize(s->stream));
   s->st.t_c = 0; s->st.t_end = 0; s->st.wp = 0; s->st.it = 0;
+  s->W = s->W0;                      // an adapted step size starts over
   s->windows = s->iterations = 0;
   s->events_base = s->runs_base = 0;
   s->last_g = 0;
@@ -872,7 +872,7 @@ extern "C" int sr_load(const void* blob, size_t n, void* stream, sr_sim** out) {
   s->last_g = h.last_g;
   if (h.tune) {
     s->tune = true;
-    s->W = h.W; s->Wmin = h.Wmin; s->Wmax = h.Wmax;
+    s->W = h.W; s->W0 = h.W; s->Wmin = h.Wmin; s->Wmax = h.Wmax;
   }
   return SR_OK;
 }
@@ -896,114 +896,27 @@ extern "C" int sr_batch_run(sr_sim* const* sims, int32_t n, void* stream_) {
 // boundaries, so the ones that must start zeroed (counts, counters, rings)
 // are cleared by one kernel over a contiguous range.
 struct BatchLayout {
-  size_t lat, run, seed, rem, ctr, q, total;
+  size_t lat, run, rem, ctr, q, total;
 };
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 static BatchLayout batch_layout(int m, uint64_t qn) {
   BatchLayout b;
   b.lat = 0;
   b.run = align256(b.lat + (size_t)m * sizeof(Lattice));
-  b.seed = align256(b.run + (size_t)m * sizeof(LatRun));          // seed_list, then seed_off
-  b.rem = align256(b.seed + ((size_t)m + kShards + 1) * sizeof(int32_t));
-  // zeroed from here on: shard counts, seed counters + queue counters, rings
+  b.rem = align256(b.run + (size_t)m * sizeof(LatRun));
   b.ctr = align256(b.rem + (size_t)m * kShards * sizeof(ShardRem));
-  b.q = align256(b.ctr + sizeof(BatchCounters) + 64 * sizeof(uint32_t));
+  b.q = align256(b.ctr + sizeof(BatchCounters));
   b.total = align256(b.q + (size_t)kShards * qn * sizeof(unsigned long long));
   return b;
 }
 
-// Host staging of one launch: caller-provided arrays of `cap` entries
-// (seed: cap + kShards + 1).
+// Host staging of one launch: caller-provided arrays of `cap` entries.
 struct BatchStage {
   Lattice* lat;
   LatRun* run;
   int* idx;
   int cap;
-  int32_t* seed;
 };
-
-// Whether the waves of a launch may pick their shard from the XCC_ID
-// register: checked once per device by recording the XCC_ID of 64
-// workgroups; pinning is used only when the ids are 0..7 and all eight
-// occur.  The probe writes into the launch's (not yet used) device block.
-constexpr int kMaxProbeDevices = 64;
-static std::mutex g_xcc_mu;
-static int8_t g_xcc_state[kMaxProbeDevices];     // 0 unknown, 1 pinning usable, 2 not
-
-static bool xcc_pinning_usable(int dev, void* scratch, hipStream_t stream) {
-  if (dev < 0 || dev >= kMaxProbeDevices) return false;
-  std::lock_guard<std::mutex> g(g_xcc_mu);
-  if (g_xcc_state[dev] == 0) {
-    uint32_t ids[64];
-    bool ok = launch_xcc_probe((uint32_t*)scratch, 64, stream) == hipSuccess &&
-              hipMemcpyAsync(ids, scratch, sizeof(ids), hipMemcpyDeviceToHost, stream) == hipSuccess &&
-              hipStreamSynchronize(stream) == hipSuccess;
-    int seen = 0;
-    for (int i = 0; ok && i < 64; ++i) {
-      if (ids[i] >= (uint32_t)kShards) ok = false;
-      else seen |= 1 << ids[i];
-    }
-    g_xcc_state[dev] = (ok && seen == (1 << kShards) - 1) ? 1 : 2;
-  }
-  return g_xcc_state[dev] == 1;
-}
-
-// Placement of a launch's lattices on XCDs.  A lattice no larger than an
-// XCD's fair share of the launch's subdomains, and whose iteration one XCD's
-// waves run at once (at most twice as many subdomains as waves per XCD),
-// runs all its tasks on one XCD: its data then stays in that XCD's L2 and
-// its deciders publish without a whole-L2 write-back.  Larger ones are
-// spread over all XCDs (pinned, their windows would take several times
-// longer, and a launch that must end at the next window boundaries waits
-// for the slowest).  Pinned lattices go heaviest first to the least-loaded
-// XCD, the weight being subdomains x remaining time x the mean class rate.
-// Fills L.xcd, the seed lists and the largest number of tasks one shard can
-// hold at once.
-static uint64_t place_lattices(sr_sim* const* sims, BatchStage& hs, int m, bool pin, uint64_t total,
-                               int waves) {
-  int32_t* list = hs.seed;
-  int32_t* off = hs.seed + m;
-  std::vector<int> pinned, spread;
-  double load[kShards] = {};
-  uint64_t tasks[kShards] = {};
-  std::vector<double> w(m);
-  for (int k = 0; k < m; ++k) {
-    const sr_sim* s = sims[hs.idx[k]];
-    double rsum = 0.0;
-    const int ncls = s->L.Lz > 1 ? kClasses3 : kClasses;
-    for (int c = 0; c < ncls; ++c) rsum += (double)s->L.rate[c];
-    w[k] = (double)s->L.nsub * (double)std::max<int64_t>(s->H - s->st.t_c, 1) * (rsum / ncls + 1.0);
-    const bool fits = pin && (uint64_t)s->L.nsub * kShards <= total && s->L.nsub <= 2 * (waves / kShards);
-    (fits ? pinned : spread).push_back(k);
-    hs.lat[k].xcd = -1;
-  }
-  for (int k : spread)
-    for (int x = 0; x < kShards; ++x) {
-      load[x] += w[k] / kShards;
-      tasks[x] += (uint64_t)(sims[hs.idx[k]]->L.nsub + kShards - 1) / kShards;
-    }
-  std::sort(pinned.begin(), pinned.end(), [&](int a, int b) { return w[a] > w[b] || (w[a] == w[b] && a < b); });
-  std::vector<std::vector<int>> bin(kShards);
-  for (int k : pinned) {
-    int best = 0;
-    for (int x = 1; x < kShards; ++x)
-      if (load[x] < load[best]) best = x;
-    load[best] += w[k];
-    tasks[best] += (uint64_t)sims[hs.idx[k]]->L.nsub;
-    hs.lat[k].xcd = best;
-    bin[best].push_back(k);
-  }
-  int at = 0;
-  for (int x = 0; x < kShards; ++x) {
-    off[x] = at;
-    for (int k : bin[x]) list[at++] = k;
-  }
-  off[kShards] = at;
-  for (int k : spread) list[at++] = k;
-  uint64_t most = 0;
-  for (int x = 0; x < kShards; ++x) most = std::max(most, tasks[x]);
-  return most;
-}
 
 // One persistent launch in flight: what batch_begin enqueued and batch_end
 // needs to collect it.
@@ -1071,33 +984,19 @@ static int batch_begin(sr_sim* const* sims, int32_t n, int32_t max_windows, hipS
   int per_cu = batch_waves_per_cu(shape, lds);
   if (per_cu <= 0) SR_FAIL(s0, SR_EDEVICE, "cannot size the persistent grid");
   int waves = std::max(per_cu * ncu, kShards);   // every shard needs a wave
-  // a shard's ring holds the current iteration of every lattice placed on
-  // it (a pinned lattice's whole iteration, a spread one's share) plus the
-  // tickets waves may hold ahead of production; sized for pinning first,
-  // the placement below can only need less
+  // a shard's ring holds its share of every lattice's current iteration
+  // (tasks are dealt round-robin, at most one extra per lattice) plus the
+  // tickets its waves may hold ahead of production
   uint64_t qn = 1;
-  while (qn < total + (uint64_t)m + (uint64_t)waves + 64) qn <<= 1;
-  BatchLayout lay = batch_layout(m, qn);
+  while (qn < total / kShards + (uint64_t)m + (uint64_t)waves / kShards + 64) qn <<= 1;
+  const BatchLayout lay = batch_layout(m, qn);
   char* base = (char*)dev;
   if (bl.fixed_mem) {
-    // the caller's block: size the rings for the placement actually chosen
-    // (decided without the probe's block, which is the same memory)
-    lay.total = 0;
-  } else if (hipMalloc((void**)&base, lay.total) != hipSuccess) {
-    SR_FAIL(s0, SR_ENOMEM, "cannot allocate the batch queue");
-  }
-  const bool pin = xcc_pinning_usable(dev_id, base, stream);
-  const uint64_t most = place_lattices(sims, hs, m, pin, total, waves);
-  uint64_t qn2 = 1;
-  while (qn2 < most + (uint64_t)m + (uint64_t)waves + 64) qn2 <<= 1;
-  qn = qn2;
-  if (bl.fixed_mem) {
-    lay = batch_layout(m, qn);
     if (lay.total > dev_cap)
       SR_FAIL(s0, SR_EINVAL, "this batch needs %zu bytes of launch memory, more than the %zu available "
               "(fewer lattices or subdomains per call)", lay.total, dev_cap);
-  } else {
-    lay = batch_layout(m, qn);           // never larger than the block allocated above
+  } else if (hipMalloc((void**)&base, lay.total) != hipSuccess) {
+    SR_FAIL(s0, SR_ENOMEM, "cannot allocate the batch queue");
   }
   bl.base = base;
   bl.owned = !bl.fixed_mem;
@@ -1112,9 +1011,7 @@ static int batch_begin(sr_sim* const* sims, int32_t n, int32_t max_windows, hipS
   unsigned long long* dq = (unsigned long long*)(base + lay.q);
   for (int k = 0; k < m; ++k) {
     sr_sim* s = sims[hs.idx[k]];
-    const int32_t xcd = hs.lat[k].xcd;      // from the placement
     hs.lat[k] = s->L;
-    hs.lat[k].xcd = xcd;
     hs.lat[k].need = s->need;
     hs.lat[k].ckint = kCkIntBatch;
     if (hipMemsetAsync(s->need, 0, 2 * (size_t)need_stride(s->L.nsub), stream) != hipSuccess) {
@@ -1135,18 +1032,12 @@ static int batch_begin(sr_sim* const* sims, int32_t n, int32_t max_windows, hipS
     // the first iteration's tasks, their per-shard counts and shards_left
     // are dealt by the kernel itself
   }
-  int32_t* dseed = (int32_t*)(base + lay.seed);
   BatchArgs args;
   args.ctr = dctr; args.q = dq; args.lat = dlat; args.run = drun; args.rem = drem;
   args.nlat = (uint32_t)m; args.qmask = (uint32_t)(qn - 1);
   args.yield = yield;
   args.notify = notify;
-  args.seed_list = dseed;
-  args.seed_off = dseed + m;
-  args.seed_next = (uint32_t*)(base + lay.ctr + sizeof(BatchCounters));
-  args.pinned_xcc = pin ? 1 : 0;
   if (launch_zero(base + lay.rem, lay.total - lay.rem, stream) != hipSuccess ||
-      hipMemcpyAsync(dseed, hs.seed, ((size_t)m + kShards + 1) * sizeof(int32_t), hipMemcpyHostToDevice, stream) != hipSuccess ||
       hipMemcpyAsync(dlat, hs.lat, m * sizeof(Lattice), hipMemcpyHostToDevice, stream) != hipSuccess ||
       hipMemcpyAsync(drun, hs.run, m * sizeof(LatRun), hipMemcpyHostToDevice, stream) != hipSuccess ||
       hipEventRecord(s0->ev[0], stream) != hipSuccess || launch_batch(args, shape, waves, lds, stream) != hipSuccess ||
@@ -1252,8 +1143,7 @@ extern "C" int sr_batch_step(sr_sim* const* sims, int32_t n, int32_t max_windows
   std::vector<Lattice> lat((size_t)n);
   std::vector<LatRun> run((size_t)n);
   std::vector<int> idx((size_t)n);
-  std::vector<int32_t> seed((size_t)n + kShards + 1);
-  BatchStage hs{lat.data(), run.data(), idx.data(), n, seed.data()};
+  BatchStage hs{lat.data(), run.data(), idx.data(), n};
   return batch_core(sims, n, max_windows, (hipStream_t)stream_, hs, nullptr, 0);
 }
 
@@ -1272,7 +1162,6 @@ static void* g_scratch_ptr[kMaxDevices];        // device address of `scratch`, 
 static Lattice g_static_lat[kStaticMaxLattices]; // host staging (no allocation per call)
 static LatRun g_static_run[kStaticMaxLattices];
 static int g_static_idx[kStaticMaxLattices];
-static int32_t g_static_seed[kStaticMaxLattices + kShards + 1];
 
 extern "C" int sr_batch_step_static(sr_sim* const* sims, int32_t n, int32_t max_windows, void* stream_) {
   if (!sims || n <= 0) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "sr_batch_step_static needs simulations");
@@ -1288,7 +1177,7 @@ extern "C" int sr_batch_step_static(sr_sim* const* sims, int32_t n, int32_t max_
       SR_FAIL(sims[0], SR_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
     g_scratch_ptr[dev] = ptr;
   }
-  BatchStage hs{g_static_lat, g_static_run, g_static_idx, kStaticMaxLattices, g_static_seed};
+  BatchStage hs{g_static_lat, g_static_run, g_static_idx, kStaticMaxLattices};
   return batch_core(sims, n, max_windows, (hipStream_t)stream_, hs, g_scratch_ptr[dev], kStaticScratchBytes);
 }
 
@@ -1342,7 +1231,6 @@ struct sr_server {
   std::vector<Lattice> st_lat;
   std::vector<LatRun> st_run;
   std::vector<int> st_idx;
-  std::vector<int32_t> st_seed;
   uint32_t* ctl = nullptr;         // pinned, host-coherent: [0] yield, [1] finished count
   bool yield_raised = false;
 };
@@ -1423,7 +1311,7 @@ extern "C" int sr_server_submit(sr_server* v, const sr_params* pin, uint64_t* re
 
 // Collect the ended launch: run records back, finished lattices retired.
 static int server_collect(sr_server* v) {
-  BatchStage hs{v->st_lat.data(), v->st_run.data(), v->st_idx.data(), (int)v->st_idx.size(), v->st_seed.data()};
+  BatchStage hs{v->st_lat.data(), v->st_run.data(), v->st_idx.data(), (int)v->st_idx.size()};
   int rc = batch_end(v->bl, hs);
   v->running = false;
   v->busy_s += server_now(v) - v->t_launch;
@@ -1442,7 +1330,7 @@ extern "C" int sr_server_pump(sr_server* v, int32_t* n_open) {
   if (!v) return SR_EINVAL;
   int rc = SR_OK;
   if (v->running) {
-    BatchStage hs{v->st_lat.data(), v->st_run.data(), v->st_idx.data(), (int)v->st_idx.size(), v->st_seed.data()};
+    BatchStage hs{v->st_lat.data(), v->st_run.data(), v->st_idx.data(), (int)v->st_idx.size()};
     // wait a little for the launch to end, so that callers can spin on pump
     for (int i = 0; i < 20 && !batch_done(v->bl, hs); ++i) {
       if (!v->yield_raised) {
@@ -1491,8 +1379,7 @@ extern "C" int sr_server_pump(sr_server* v, int32_t* n_open) {
     v->st_lat.resize(m);
     v->st_run.resize(m);
     v->st_idx.resize(m);
-    v->st_seed.resize(m + kShards + 1);
-    BatchStage hs{v->st_lat.data(), v->st_run.data(), v->st_idx.data(), (int)m, v->st_seed.data()};
+    BatchStage hs{v->st_lat.data(), v->st_run.data(), v->st_idx.data(), (int)m};
     __atomic_store_n(&v->ctl[0], 0u, __ATOMIC_RELEASE);
     __atomic_store_n(&v->ctl[1], 0u, __ATOMIC_RELEASE);
     v->yield_raised = false;
@@ -1543,7 +1430,7 @@ extern "C" void sr_server_destroy(sr_server* v) {
   if (v->running) {
     // end the launch at the next window boundaries, then collect it
     __atomic_store_n(&v->ctl[0], 1u, __ATOMIC_RELEASE);
-    BatchStage hs{v->st_lat.data(), v->st_run.data(), v->st_idx.data(), (int)v->st_idx.size(), v->st_seed.data()};
+    BatchStage hs{v->st_lat.data(), v->st_run.data(), v->st_idx.data(), (int)v->st_idx.size()};
     (void)batch_end(v->bl, hs);
     v->running = false;
   }

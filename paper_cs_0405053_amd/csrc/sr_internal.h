@@ -91,8 +91,6 @@ struct Lattice {
   int32_t wcap;           // entries per subdomain window log
   int32_t wipe;           // step rule: 1 = every window start t_c > 0 drops
                           // the pending pair (wipe the slate, Sec. 5)
-  int32_t xcd;            // batched form: the XCD (L2 domain) that runs every
-                          // task of this lattice, or -1 (spread over all)
   // Double buffers are single allocations; buffer q starts at base + q * stride.
   int8_t* spins;          // 2 x Lx*Ly: committed lattice, by window parity
   Carry* carry;           // 2 x nsub: by window parity
@@ -229,13 +227,6 @@ struct BatchArgs {             // read-only for the kernel's lifetime
   // can admit and retire; `notify` counts lattices that reached their horizon
   const uint32_t* yield;
   uint32_t* notify;
-  // lattices whose first iteration each XCD deals: seed_list[seed_off[x] ..
-  // seed_off[x + 1]) for XCD x < kShards, [seed_off[kShards], nlat) for the
-  // spread lattices (any XCD); seed_next[x] hands them out (zeroed)
-  const int32_t* seed_list;
-  const int32_t* seed_off;     // kShards + 1 entries
-  uint32_t* seed_next;         // kShards + 1 counters
-  int32_t pinned_xcc;          // 1: shard = the wave's XCC_ID (checked 0..7)
 };
 
 }  // namespace sr

@@ -648,31 +648,25 @@ __device__ __forceinline__ Step step_of(const RunView& v) {
 // others keep their lists: the slot array is copied forward and the change
 // masks cleared before anything is published.  Sets the per-shard counts
 // and shards_left before publishing any task.
-// Ordering between the tasks of one lattice.  A task's results are written
-// with device-coherent stores (through to the point where all XCDs' reads
-// meet), so a task publishes by waiting for its stores; it starts with the
-// device-scope acquire, which invalidates this CU's L1 and the L2's copies of
-// other XCDs' data (the workgroup-scope L1 invalidate is not enough: outside
-// threadgroup-split mode it left stale L1 lines visible to the next task,
-// measured as wrong trajectories).  The decider writes with ordinary stores:
-// for a lattice spread over every XCD it publishes with the device-scope
-// release, which writes the whole L2 back and which the L2 serialises (once
-// per task it took over half of the batched form's time); a lattice pinned to
-// one XCD keeps all its data in that XCD's L2, which every CU of the XCD
-// shares and which L1 writes through to, so there too a wait suffices.
-__device__ __forceinline__ void task_release() { __asm__ volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory"); }
-__device__ __forceinline__ void lattice_release(bool pinned) {
-  if (pinned) {
-    task_release();
-  } else {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  }
-}
+// Ordering between the tasks of one lattice.  Everything the batched form
+// writes for other waves (a run's results, the decider's run record, slot
+// and change arrays, counts) goes out with device-coherent stores, written
+// through to the point where every XCD's reads meet: publishing then only
+// waits for those stores, with no L2 write-back.  (A device-scope release
+// writes the whole L2 back and the L2 serialises it: issued once per task,
+// it took over half of the batched form's time.)  A task starts with the
+// device-scope acquire, which invalidates this CU's L1 and the L2's copies
+// of lines other XCDs wrote (the workgroup-scope L1 invalidate is not
+// enough: outside threadgroup-split mode it left stale L1 lines visible to
+// the next task, measured as wrong trajectories).
+__device__ __forceinline__ void publish_wait() { __asm__ volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory"); }
 __device__ __forceinline__ void lattice_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 
-// The XCD (XCC) this wave runs on: hardware register XCC_ID, bits 3:0.
-__device__ __forceinline__ int wave_xcc() {
-  return (int)__builtin_amdgcn_s_getreg((20) | (0 << 6) | (3 << 11)) & 15;
+// Device-coherent copy of 16 bytes (two 8-byte stores).
+__device__ __forceinline__ void gput16(uint4* p, const uint4& v) {
+  unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
+  gput<true>(q, ((unsigned long long)v.y << 32) | v.x);
+  gput<true>(q + 1, ((unsigned long long)v.w << 32) | v.z);
 }
 
 __device__ uint32_t enqueue_iteration(const BatchArgs& B, int lat, LatRun* run, CLattice& L, int it,
@@ -710,8 +704,8 @@ __device__ uint32_t enqueue_iteration(const BatchArgs& B, int lat, LatRun* run, 
     const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll 4
     for (int i = lane; i < n16; i += 64) {
-      sn[i] = sp[i];
-      cn[i] = zero;
+      gput16(&sn[i], sp[i]);
+      gput16(&cn[i], zero);
     }
   }
   uint32_t count = 0;
@@ -725,22 +719,17 @@ __device__ uint32_t enqueue_iteration(const BatchArgs& B, int lat, LatRun* run, 
   }
   count = (uint32_t)wave_sum64(count);
   if (count == 0) return 0;                     // caller turns this into an error
-  // spread lattice: task i of the iteration goes to shard (off + i) %
-  // kShards, the (i / kShards)-th of that shard; pinned lattice: every task
-  // to its XCD's shard, the i-th of it.  Lane s < kShards handles shard s.
-  const int xcd = L.xcd;
-  const bool pinned = xcd >= 0;
+  // task i of the iteration goes to shard (off + i) % kShards, the
+  // (i / kShards)-th of that shard; lane s < kShards handles shard s
   const int off = lat % kShards;
   const int ls = (lane - off + kShards) % kShards;         // first task index of shard `lane`
-  const uint32_t ns = lane < kShards ? (pinned ? (lane == xcd ? count : 0u)
-                                               : (count > (uint32_t)ls ? (count - 1 - ls) / kShards + 1 : 0u))
-                                     : 0u;
-  if (lane < kShards) B.rem[(size_t)lat * kShards + lane].n = (int32_t)ns;
+  const uint32_t ns = lane < kShards ? (count > (uint32_t)ls ? (count - 1 - ls) / kShards + 1 : 0u) : 0u;
+  if (lane < kShards) gput<true>(&B.rem[(size_t)lat * kShards + lane].n, (int32_t)ns);
   if (lane == 0) {
-    run->shards_left = pinned ? 1 : (int32_t)(count < (uint32_t)kShards ? count : (uint32_t)kShards);
-    run->tasks += count;
+    gput<true>(&run->shards_left, (int32_t)(count < (uint32_t)kShards ? count : (uint32_t)kShards));
+    gput<true>(&run->tasks, run->tasks + count);
   }
-  lattice_release(pinned);
+  publish_wait();
   unsigned long long sbase = 0;
   if (lane < kShards && ns) sbase = atomicAdd(&B.ctr->sh[lane].tail, (unsigned long long)ns);
   unsigned long long bases[kShards];           // wave-uniform, read before the divergent walk
@@ -749,16 +738,15 @@ __device__ uint32_t enqueue_iteration(const BatchArgs& B, int lat, LatRun* run, 
   const size_t qn = (size_t)B.qmask + 1;
   if (it == 0) {
     // every subdomain runs: task i is subdomain i, in shard (off + i) mod
-    // kShards at position i / kShards (pinned: in its XCD's shard at
-    // position i); 64 is a multiple of kShards, so a lane's shard is the same
-    // in every round
-    const int sh = pinned ? xcd : (off + lane) % kShards;
+    // kShards at position i / kShards; 64 is a multiple of kShards, so a
+    // lane's shard is the same in every round
+    const int sh = (off + lane) % kShards;
     unsigned long long base = bases[0];
 #pragma unroll
     for (int k = 1; k < kShards; ++k) base = sh == k ? bases[k] : base;
     unsigned long long* qs = B.q + (size_t)sh * qn;
     for (int d = lane; d < nsub; d += 64) {
-      const unsigned long long at = base + (pinned ? (unsigned)d : (unsigned)d / kShards);
+      const unsigned long long at = base + (unsigned)d / kShards;
       __hip_atomic_store(&qs[at & B.qmask], ((at + 1) << 32) | ((unsigned long long)lat << 20) | (unsigned)d,
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -776,11 +764,11 @@ __device__ uint32_t enqueue_iteration(const BatchArgs& B, int lat, LatRun* run, 
       const int bit = ctz64(m);
       m &= m - 1;
       const int d = (w0 + lane) * 64 + bit;
-      const int sh = pinned ? xcd : (int)((off + i) % kShards);
+      const int sh = (int)((off + i) % kShards);
       unsigned long long base = bases[0];
 #pragma unroll
       for (int k = 1; k < kShards; ++k) base = sh == k ? bases[k] : base;
-      const unsigned long long at = base + (pinned ? i : i / kShards);
+      const unsigned long long at = base + i / kShards;
       const unsigned long long v = ((at + 1) << 32) | ((unsigned long long)lat << 20) | (unsigned)d;
       __hip_atomic_store(&B.q[(size_t)sh * qn + (at & B.qmask)], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       i++;
@@ -790,12 +778,17 @@ __device__ uint32_t enqueue_iteration(const BatchArgs& B, int lat, LatRun* run, 
   return count;
 }
 
+// Device-coherent store of a run record's step.
+__device__ __forceinline__ void put_step(Step* p, const Step& st) {
+  gput<true>(&p->t_c, st.t_c); gput<true>(&p->t_end, st.t_end);
+  gput<true>(&p->wp, st.wp); gput<true>(&p->it, st.it); gput<true>(&p->fi, st.fi);
+}
+
 // The last task of an iteration of lattice `lat`: compare step (c) of the
 // Sec. 4 box for the whole lattice, then the next iteration, the next
 // window (committed time advances), or completion.
 __device__ void decide(const BatchArgs& B, int lat, int lane) {
   CLattice& L = ((CLattice*)B.lat)[lat];
-  const bool pinned = L.xcd >= 0;
   lattice_acquire();
   LatRun* run = &B.run[lat];
   const RunView rv = load_run(run, lane);
@@ -810,14 +803,14 @@ __device__ void decide(const BatchArgs& B, int lat, int lane) {
   const int32_t win_budget = (int32_t)rv.u32(offsetof(LatRun, win_budget));
   const int64_t H = rv.i64(offsetof(LatRun, H));
   bool finish = false;
-  if (lane == 0) run->iterations = rv.i64(offsetof(LatRun, iterations)) + 1;
+  if (lane == 0) gput<true>(&run->iterations, rv.i64(offsetof(LatRun, iterations)) + 1);
   int next_it = -1;
   if (f.ovf_hist || f.ovf_log) {
-    if (lane == 0) run->status = kOverflow;
+    if (lane == 0) gput<true>(&run->status, (int32_t)kOverflow);
     finish = true;
   } else if (f.changed) {
     if (st.it + 1 >= max_iters) {
-      if (lane == 0) run->status = kNoConv;
+      if (lane == 0) gput<true>(&run->status, (int32_t)kNoConv);
       finish = true;
     } else {
       next_it = st.it + 1;
@@ -828,18 +821,18 @@ __device__ void decide(const BatchArgs& B, int lat, int lane) {
     st.t_c = st.t_end;
     const int64_t wins = rv.i64(offsetof(LatRun, windows)) + 1;
     if (lane == 0) {
-      run->windows = wins;
-      run->last_g = st.it + 1;
+      gput<true>(&run->windows, wins);
+      gput<true>(&run->last_g, st.it + 1);
     }
     int64_t W = rv.i64(offsetof(LatRun, W));
     if (tune) {
       W = tune_window(W, st.it + 1, rv.i64(offsetof(LatRun, Wmin)), rv.i64(offsetof(LatRun, Wmax)));
-      if (lane == 0) run->W = W;
+      if (lane == 0) gput<true>(&run->W, W);
     }
     if (st.t_c >= H) {
       if (lane == 0) {
-        run->status = kDone;
-        run->st = st;
+        gput<true>(&run->status, (int32_t)kDone);
+        put_step(&run->st, st);
         if (B.notify) __hip_atomic_fetch_add(B.notify, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
       }
       finish = true;
@@ -847,7 +840,7 @@ __device__ void decide(const BatchArgs& B, int lat, int lane) {
                (B.yield && __hip_atomic_load(B.yield, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0u)) {
       // this launch's share of windows is done, or the host asked the launch
       // to end: pause at committed time
-      if (lane == 0) { run->status = kPaused; run->st = st; }
+      if (lane == 0) { gput<true>(&run->status, (int32_t)kPaused); put_step(&run->st, st); }
       finish = true;
     } else {
       st.t_end = min64(st.t_c + W, H);
@@ -855,20 +848,20 @@ __device__ void decide(const BatchArgs& B, int lat, int lane) {
     }
   }
   if (finish) {
-    lattice_release(pinned);
+    publish_wait();
     if (lane == 0) atomicAdd(&B.ctr->done, 1u);
     return;
   }
   st.it = next_it;
   st.fi = 0;
   if (lane == 0) {
-    run->st = st;
-    run->fl.changed = 0; run->fl.ovf_hist = 0; run->fl.ovf_log = 0;
+    put_step(&run->st, st);
+    gput<true>(&run->fl.changed, 0u); gput<true>(&run->fl.ovf_hist, 0u); gput<true>(&run->fl.ovf_log, 0u);
   }
   if (enqueue_iteration(B, lat, run, L, next_it, lane) == 0) {
     // a changed iteration must schedule some subdomain; never wait forever
-    if (lane == 0) run->status = kBad;
-    lattice_release(pinned);
+    if (lane == 0) gput<true>(&run->status, (int32_t)kBad);
+    publish_wait();
     if (lane == 0) atomicAdd(&B.ctr->done, 1u);
   }
 }
@@ -881,11 +874,10 @@ __device__ void decide(const BatchArgs& B, int lat, int lane) {
 constexpr uint32_t kSpinBudget = 20u << 20;
 constexpr uint32_t kProgressEvery = 4096;
 
-// Shard g is the queue of XCD g: a wave serves the shard of the XCD it runs
-// on (its XCC_ID register; without pinning, workgroup w % kShards, which the
-// dispatcher places on XCD w % kShards), so a pinned lattice's tasks and its
-// decider all run on its XCD.  Per task: wait for the slot of the ticket held,
-// acquire, relax, release, count the task down while taking the next ticket.
+// Wave w serves shard w % kShards (the dispatcher places workgroup w on XCD
+// w % kShards, so each shard's counters are hit from one XCD).  Per task:
+// wait for the slot of the ticket held, acquire, relax, publish, count the
+// task down while taking the next ticket.
 // A held ticket whose task is not produced yet blocks no one: tasks are
 // produced by deciders, and a wave finishes its current task before it waits.
 // Registers are capped so that six waves share a SIMD (80 VGPRs; the few
@@ -900,27 +892,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   extern __shared__ int8_t tile[];
   const int lane = lane_id();
   CLattice* lats = (CLattice*)B.lat;
-  // the wave serves the shard of the XCD it runs on (pinned lattices keep
-  // all their tasks there); without pinning, the shard of its workgroup id
-  const int g = B.pinned_xcc ? (wave_xcc() & (kShards - 1)) : (int)(blockIdx.x % kShards);
+  const int g = (int)(blockIdx.x % kShards);
   ShardCtr* sc = &B.ctr->sh[g];
   const unsigned long long* qg = B.q + (size_t)g * ((size_t)B.qmask + 1);
-  // the first iteration of every lattice (all its subdomains) is dealt
-  // before the wave takes a ticket: this XCD's pinned lattices, then spread
-  // ones, each handed out once; tasks are taken as they appear
-  for (int part = 0; part < 2; ++part) {
-    const int x = part == 0 ? g : kShards;
-    if (part == 0 && !B.pinned_xcc) continue;
-    const int lo = B.seed_off[x], n = (x == kShards ? (int)B.nlat : B.seed_off[x + 1]) - lo;
-    for (;;) {
-      uint32_t i = 0;
-      if (lane == 0) i = atomicAdd(&B.seed_next[x], 1u);
-      i = rdl(i, 0);
-      if ((int)i >= n) break;
-      const int k = B.seed_list[lo + (int)i];
-      enqueue_iteration(B, k, &B.run[k], lats[k], 0, lane);
-    }
-  }
+  // the first iteration of every lattice (all its subdomains) is dealt by
+  // the grid before any wave takes a ticket; tasks are taken as they appear
+  for (int k = blockIdx.x; k < (int)B.nlat; k += gridDim.x)
+    enqueue_iteration(B, k, &B.run[k], lats[k], 0, lane);
   unsigned long long t = 0;
   if (lane == 0) t = atomicAdd(&sc->head, 1ull);
   t = ((uint64_t)rdl((uint32_t)(t >> 32), 0) << 32) | rdl((uint32_t)t, 0);
@@ -962,7 +940,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     // (convergent no-ops around it keep one wait, executed by the whole wave,
     // instead of one in each lane-0 region the compiler would merge it into)
     __builtin_amdgcn_wave_barrier();
-    task_release();
+    publish_wait();
     __builtin_amdgcn_wave_barrier();
     // count this task down and take the next ticket: both memory-side
     // atomics are in flight together
@@ -1094,16 +1072,6 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t stream) {
 // 7.87e7 and 6.31e7 / 6.17e7 / 6.15e7.
 static const void* batch_kernel_for(int shape) {
   return shape == kBatch16NoWrap ? (const void*)batch_kernel<16, 16, true, 6> : (const void*)batch_kernel<0, 0, false, 6>;
-}
-
-// Each workgroup records the XCD (XCC_ID) it ran on.
-__global__ void xcc_probe_kernel(uint32_t* out, int n) {
-  if (threadIdx.x == 0 && (int)blockIdx.x < n) out[blockIdx.x] = (uint32_t)wave_xcc();
-}
-
-hipError_t launch_xcc_probe(uint32_t* out, int n, hipStream_t stream) {
-  hipLaunchKernelGGL(xcc_probe_kernel, dim3((unsigned)n), dim3(64), 0, stream, out, n);
-  return hipGetLastError();
 }
 
 hipError_t launch_batch(const BatchArgs& B, int shape, int waves, size_t lds, hipStream_t stream) {

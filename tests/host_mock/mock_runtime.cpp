@@ -267,10 +267,6 @@ hipError_t launch_batch(const BatchArgs& B, int, int, size_t, hipStream_t) {
   return hipSuccess;
 }
 // workgroups land on XCDs 0..7 in turn, as on the device
-hipError_t launch_xcc_probe(uint32_t* out, int n, hipStream_t) {
-  for (int i = 0; i < n; ++i) out[i] = (uint32_t)(i % 8);
-  return hipSuccess;
-}
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t) {
   std::memset(p, 0, bytes);
   return hipSuccess;

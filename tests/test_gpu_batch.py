@@ -211,3 +211,35 @@ def test_both_persistent_kernels_equal_plain_and_oracle(monkeypatch, kernel):
     assert np.array_equal(sims[3].digests()[0], ref["sub_digest"])
     for s in sims:
         s.close()
+
+
+def test_reset_repeats_the_same_work():
+    # a reset simulation starts over with the step size chosen at creation:
+    # the same windows, iterations and re-simulated events come back, in the
+    # batched and in the plain form (a tuned step size adapts during a run)
+    sr = _sr()
+    ps = [dict(p, window=0.0) for p in mix(n=6, seed=21)]
+    sims = [sr.Sim(p) for p in ps]
+
+    def work():
+        return [(o["windows"], o["iterations"], o["events_processed"], o["window_ticks"])
+                for o in (s.observables() for s in sims)]
+
+    sr.batch_run(sims)
+    first, st1 = work(), [state(s) for s in sims]
+    for s in sims:
+        s.reset()
+    sr.batch_run(sims)
+    assert work() == first
+    assert all(same(state(s), a) for s, a in zip(sims, st1))
+    for s in sims:
+        s.close()
+    s = sr.Sim(ps[0])
+    g1 = s.run()
+    o1 = s.observables()
+    s.reset()
+    g2 = s.run()
+    o2 = s.observables()
+    s.close()
+    assert np.array_equal(g1, g2)
+    assert (o1["events_processed"], o1["window_ticks"]) == (o2["events_processed"], o2["window_ticks"])
