@@ -20,6 +20,18 @@ __device__ __forceinline__ uint32_t rdl(uint32_t v, int l) {
 __device__ __forceinline__ uint64_t rdl64(uint64_t v, int l) {
   return (uint64_t)rdl((uint32_t)v, l) | ((uint64_t)rdl((uint32_t)(v >> 32), l) << 32);
 }
+// v with lane L's word replaced by the uniform value x (two v_writelane;
+// this compiler has no builtin for it, and the asm reads and writes only
+// registers).
+template <int L>
+__device__ __forceinline__ uint64_t wrl64(uint64_t v, uint64_t x) {
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+  const uint32_t xl = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+  const uint32_t xh = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+  __asm__("v_writelane_b32 %0, %1, %2" : "+v"(lo) : "s"(xl), "i"(L));
+  __asm__("v_writelane_b32 %0, %1, %2" : "+v"(hi) : "s"(xh), "i"(L));
+  return (uint64_t)lo | ((uint64_t)hi << 32);
+}
 __device__ __forceinline__ int ctz64(uint64_t m) { return __builtin_ctzll(m); }
 __device__ __forceinline__ int64_t min64(int64_t a, int64_t b) { return a < b ? a : b; }
 

@@ -336,19 +336,21 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
       const uint32_t clo = (uint32_t)__shfl((int)ncnt, (2 * lane) & 63, 64);
       const uint32_t chi = (uint32_t)__shfl((int)ncnt, (2 * lane + 1) & 63, 64);
       uint64_t w = (uint64_t)clo | ((uint64_t)chi << 32);
-      w = lane == kCkT ? (uint64_t)tn : w;
-      w = lane == kCkJ ? j : w;
-      w = lane == kCkAcc ? acc : w;
-      w = lane == kCkAnchor ? (uint64_t)anchor : w;
-      w = lane == kCkHalo + 0 ? hN : w;
-      w = lane == kCkHalo + 1 ? hS : w;
-      w = lane == kCkHalo + 2 ? hW : w;
-      w = lane == kCkHalo + 3 ? hE : w;
-      w = lane == kCkDsum ? dtot : w;
-      w = lane == kCkNev ? ((uint64_t)(uint32_t)nev | ((uint64_t)(uint32_t)nbound << 32)) : w;
-      w = lane == kCkOut01 ? ((uint64_t)(uint32_t)nN | ((uint64_t)(uint32_t)nS << 32)) : w;
-      w = lane == kCkOut23 ? ((uint64_t)(uint32_t)nW | ((uint64_t)(uint32_t)nE << 32)) : w;
-      w = lane == kCkHead ? (uint64_t)(uint32_t)in.head : w;
+      // the scalar words go in with lane writes (no per-lane selects, so no
+      // lane masks kept live across the event loop)
+      w = wrl64<kCkT>(w, (uint64_t)tn);
+      w = wrl64<kCkJ>(w, j);
+      w = wrl64<kCkAcc>(w, acc);
+      w = wrl64<kCkAnchor>(w, (uint64_t)anchor);
+      w = wrl64<kCkHalo + 0>(w, hN);
+      w = wrl64<kCkHalo + 1>(w, hS);
+      w = wrl64<kCkHalo + 2>(w, hW);
+      w = wrl64<kCkHalo + 3>(w, hE);
+      w = wrl64<kCkDsum>(w, dtot);
+      w = wrl64<kCkNev>(w, (uint64_t)(uint32_t)nev | ((uint64_t)(uint32_t)nbound << 32));
+      w = wrl64<kCkOut01>(w, (uint64_t)(uint32_t)nN | ((uint64_t)(uint32_t)nS << 32));
+      w = wrl64<kCkOut23>(w, (uint64_t)(uint32_t)nW | ((uint64_t)(uint32_t)nE << 32));
+      w = wrl64<kCkHead>(w, (uint64_t)(uint32_t)in.head);
       if (lane < 32) gput<COH>(&c->meta[lane], lane < kCkWords ? w : 0ull);
       ckc++;
       since = 0;
