@@ -683,12 +683,16 @@ __device__ uint32_t enqueue_iteration(const BatchArgs& B, int lat, LatRun* run, 
       const int left = nsub - w * 64;
       return left >= 64 ? ~0ull : ((1ull << left) - 1);
     }
-    // one 16-byte load at a time (fewer registers live in the decider)
+    // the four 16-byte loads in flight together (one round trip on the
+    // decider's path instead of four)
     const uint4* p = reinterpret_cast<const uint4*>(nb + (size_t)w * 64);
+    uint4 xs[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) xs[k] = p[k];
     unsigned long long m = 0;
-#pragma unroll 1
+#pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const uint4 x = p[k];
+      const uint4 x = xs[k];
       const unsigned long long lo = ((unsigned long long)x.y << 32) | x.x;
       const unsigned long long hi = ((unsigned long long)x.w << 32) | x.z;
       m |= (((lo & 0x0101010101010101ull) * 0x0102040810204080ull) >> 56) << (16 * k);
