@@ -32,6 +32,17 @@ __device__ __forceinline__ uint64_t wrl64(uint64_t v, uint64_t x) {
   __asm__("v_writelane_b32 %0, %1, %2" : "+v"(hi) : "s"(xh), "i"(L));
   return (uint64_t)lo | ((uint64_t)hi << 32);
 }
+// The same for a lane chosen at run time (a uniform index).
+__device__ __forceinline__ uint64_t wrl64_at(uint64_t v, uint64_t x, int l) {
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+  const uint32_t xl = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+  const uint32_t xh = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+  const int ls = __builtin_amdgcn_readfirstlane(l);
+  // a VALU instruction reads one SGPR besides M0: the lane select goes in M0
+  __asm__("s_mov_b32 m0, %4\n\ts_nop 0\n\tv_writelane_b32 %0, %2, m0\n\tv_writelane_b32 %1, %3, m0"
+          : "+v"(lo), "+v"(hi) : "s"(xl), "s"(xh), "s"(ls) : "m0");
+  return (uint64_t)lo | ((uint64_t)hi << 32);
+}
 __device__ __forceinline__ int ctz64(uint64_t m) { return __builtin_ctzll(m); }
 __device__ __forceinline__ int64_t min64(int64_t a, int64_t b) { return a < b ? a : b; }
 

@@ -394,7 +394,29 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
       const int kv = (int)((rdl64(cls, v & 63) >> ((v >> 6) * 4)) & 15);
       const bool now_up = kv >= 5;
       const int dup = now_up ? 1 : -1;
-      if ((bx >= 3 || !wrapx) && (by >= 3 || !wrapy)) {
+      if constexpr (BX == 16 && BY == 16 && NW) {
+        // 16x16 block, no wrap: the five sites sit in five different lanes
+        // (their index differences 1, 2, 15, 16, 17, 32 are never multiples
+        // of 64), so each class word is read, moved on the scalar unit and
+        // written back to its lane
+        const int dv = now_up ? -5 : 5;
+        uint32_t inc = (uint32_t)(lane == kv + dv), dec = (uint32_t)(lane == kv);
+        cls = wrl64_at(cls, rdl64(cls, v & 63) + ((uint64_t)(int64_t)dv << ((v >> 6) * 4)), v & 63);
+        const int nbr[4] = {lx > 0 ? v - 1 : -1, lx < 15 ? v + 1 : -1, ly > 0 ? v - 16 : -1,
+                            ly < 15 ? v + 16 : -1};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int u = nbr[q];
+          if (u < 0) continue;
+          const int o = u & 63, sl = (u >> 6) * 4;
+          const uint64_t w = rdl64(cls, o);
+          const int a = (int)((w >> sl) & 15);
+          cls = wrl64_at(cls, w + ((uint64_t)(int64_t)dup << sl), o);
+          inc += (uint32_t)(lane == a + dup);
+          dec += (uint32_t)(lane == a);
+        }
+        ncnt += inc - dec;
+      } else if ((bx >= 3 || !wrapx) && (by >= 3 || !wrapy)) {
         // the flipped site and its in-block neighbours are five distinct
         // sites: read every old class from the words before the flip and
         // apply all the moves at once (no chain through the class words)
