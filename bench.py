@@ -43,6 +43,8 @@ LDS_PEAK_GBPS = 256 * 128 * 2.4e9 / 1e9       # 128 B per clock per CU
 # (64 lanes) ~10.
 WAVE_INSTR_PER_EVENT = 200
 HBM_PEAK_GBPS = 8000.0
+# LDS: 128 bytes per cycle per CU
+LDS_PEAK_GBPS = 256 * 128 * 2.4e9 / 1e9
 METRIC = "committed flips/s + relax iters/window, batched vs plain, bit-exact on 1 GPU"
 
 
@@ -286,8 +288,9 @@ def bench_batch(sr, W, stream, torch, args, nstreams=8):
 
 def add_counters(roof, name, avg_launch_s, processed):
     """Counter-derived figures of the same kernel source (profiles/): HBM
-    bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated) and issued
-    instructions per launch (SQ_INSTS_VALU / SALU)."""
+    bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated), issued
+    instructions per launch (SQ_INSTS_VALU / SALU) and LDS bytes per launch
+    ((SQ_LDS_IDX_ACTIVE - SQ_LDS_BANK_CONFLICT) cycles x 128 B)."""
     tr = profile_record(f"{name}_traffic.json")
     if tr:
         roof["traffic"] = tr["bytes_per_launch"]
@@ -303,6 +306,11 @@ def add_counters(roof, name, avg_launch_s, processed):
             "salu_frac": round(ins["salu_per_launch"] / avg_launch_s / PEAK_WAVE_INSTR, 4),
             "instr_per_processed_event": round(per / max(processed, 1), 1),
             "source": f"profiles/{name}_instructions.json"}
+        lds = ins.get("lds")
+        if lds:
+            b = lds["bytes_per_launch"]
+            roof["lds_GBps"] = round(b / avg_launch_s / 1e9, 1)
+            roof["lds_frac"] = round(b / avg_launch_s / 1e9 / LDS_PEAK_GBPS, 4)
 
 
 # ------------------------------------------------------------------ medium
