@@ -65,19 +65,30 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
   return x;
 }
 
-// Inclusive prefix sum of 64-bit values within each row of 16 lanes.
-template <int SH>
-__device__ __forceinline__ uint64_t row_step64(uint64_t x) {
-  uint32_t lo = dpp0<0x110 + SH, 0xf>((uint32_t)x);
-  uint32_t hi = dpp0<0x110 + SH, 0xf>((uint32_t)(x >> 32));
-  return x + (((uint64_t)hi << 32) | lo);
-}
+// Inclusive prefix sum of 64-bit values within each row of 16 lanes, four
+// Hillis-Steele steps (row_shr 1, 2, 4, 8).  Each step is one 64-bit add
+// whose first operand is the row-shifted value: a carry-out add and a
+// carry-in add with the DPP shift applied to them directly.  Lanes whose
+// source lies outside the row are disabled by DPP (bound_ctrl off) and keep
+// their value, which is what adding 0 gives.  A DPP read of a register that
+// a VALU instruction just wrote needs two wait states: `s_nop 1` before each
+// step.  The asm touches registers and VCC only.
 __device__ __forceinline__ uint64_t row_incl_scan64(uint64_t x) {
-  x = row_step64<1>(x);
-  x = row_step64<2>(x);
-  x = row_step64<4>(x);
-  x = row_step64<8>(x);
-  return x;
+  uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+  __asm__("s_nop 1\n\t"
+          "v_add_co_u32_dpp %0, vcc, %0, %0 row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+          "v_addc_co_u32_dpp %1, vcc, %1, %1, vcc row_shr:1 row_mask:0xf bank_mask:0xf\n\t"
+          "s_nop 1\n\t"
+          "v_add_co_u32_dpp %0, vcc, %0, %0 row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+          "v_addc_co_u32_dpp %1, vcc, %1, %1, vcc row_shr:2 row_mask:0xf bank_mask:0xf\n\t"
+          "s_nop 1\n\t"
+          "v_add_co_u32_dpp %0, vcc, %0, %0 row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+          "v_addc_co_u32_dpp %1, vcc, %1, %1, vcc row_shr:4 row_mask:0xf bank_mask:0xf\n\t"
+          "s_nop 1\n\t"
+          "v_add_co_u32_dpp %0, vcc, %0, %0 row_shr:8 row_mask:0xf bank_mask:0xf\n\t"
+          "v_addc_co_u32_dpp %1, vcc, %1, %1, vcc row_shr:8 row_mask:0xf bank_mask:0xf"
+          : "+v"(lo), "+v"(hi) : : "vcc");
+  return (uint64_t)lo | ((uint64_t)hi << 32);
 }
 
 // ------------------------------------------------------------ random numbers
