@@ -895,8 +895,8 @@ __device__ void decide(const BatchArgs& B, int lat, int lane) {
 }
 
 // Empty polls of one queue slot, with no task finished anywhere in the grid
-// meanwhile, before the kernel gives up (about ten seconds; a task takes
-// microseconds to milliseconds).  Progress is the sum of the shards' ticket
+// meanwhile, before the kernel gives up (tens of seconds at the longest
+// back-off; a task takes microseconds to milliseconds).  Progress is the sum of the shards' ticket
 // counters (every finished task takes a ticket), read every kProgressEvery
 // polls; a wave whose shard has no work while others do keeps waiting.
 constexpr uint32_t kSpinBudget = 20u << 20;
@@ -933,13 +933,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   for (;;) {
     const uint32_t want = (uint32_t)(t + 1);
     unsigned long long v;
-    uint32_t spins = 0;
+    uint32_t spins = 0, polls = 0;
     unsigned long long seen = 0;
     for (;;) {
       v = __hip_atomic_load(&qg[t & B.qmask], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if ((uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32)) == want) break;
-      if (__hip_atomic_load(&B.ctr->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= B.nlat) return;
-      if (__hip_atomic_load(&B.ctr->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+      if ((++polls & 7) == 0) {
+        if (__hip_atomic_load(&B.ctr->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= B.nlat) return;
+        if (__hip_atomic_load(&B.ctr->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+      }
       if (++spins % kProgressEvery == 0) {
         unsigned long long prog = 0;
 #pragma unroll
@@ -954,7 +956,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
         if (lane == 0) __hip_atomic_store(&B.ctr->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return;
       }
-      __builtin_amdgcn_s_sleep(2);
+      // back off: with few lattices most waves wait for the next iteration's
+      // tasks, and their polls would compete with the running tasks' memory
+      // traffic (a slot still empty after a few polls waits for a decider,
+      // microseconds away)
+      if (polls < 4) __builtin_amdgcn_s_sleep(1);
+      else if (polls < 32) __builtin_amdgcn_s_sleep(8);
+      else __builtin_amdgcn_s_sleep(32);
     }
     // the task is wave-uniform: keep it (and all that derives from it) scalar
     const uint32_t pay = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
