@@ -156,7 +156,13 @@ int sr_create(const sr_params* p, void* hip_stream, sr_sim** out);
  * it must be NULL (SR_EINVAL otherwise), because a tuned step size makes the
  * number of windows unknown in advance.  *n_done (may be NULL) = windows
  * committed.  On SR_ENOCONV the failing window is left uncommitted and
- * earlier ones stay. */
+ * earlier ones stay.  A window that overflows a boundary list or the window
+ * log is redone with larger buffers; at their capacity limits (1024 list
+ * entries, 448 in 3D; 2^22 log entries) the step size is halved instead and
+ * stays so (the continue rule's trajectory does not depend on it, so the
+ * committed events are the same, in more windows), while under
+ * SR_STEP_WIPE, whose trajectory depends on the step size, the call returns
+ * SR_EOVERFLOW with the window uncommitted. */
 int sr_run_window(sr_sim* s, int32_t n_windows, int32_t* iters_out, int32_t* n_done);
 
 /* Observables at committed time (eq. hamil parts): M, bond sum, counters. */

@@ -470,6 +470,8 @@ extern "C" const char* sr_last_error(const sr_sim* s) {
 }
 
 // ------------------------------------------------------------ window loop
+constexpr int32_t kMaxWcap = 1 << 22;   // window log entries per subdomain
+
 static int grow(sr_sim* s, uint32_t ovf) {
   Lattice& L = s->L;
   if (ovf & 1u) {
@@ -478,11 +480,35 @@ static int grow(sr_sim* s, uint32_t ovf) {
     L.hcap = std::min(2 * L.hcap, cap);
   }
   if (ovf & 2u) {
-    if (L.wcap >= (1 << 22)) SR_FAIL(s, SR_EOVERFLOW, "window log capacity limit reached");
+    if (L.wcap >= kMaxWcap) SR_FAIL(s, SR_EOVERFLOW, "window log capacity limit reached");
     L.wcap *= 2;
   }
   free_hist(s);
   return alloc_hist(s);
+}
+
+// A window of `span` ticks overflowed its boundary lists (bit 0 of ovf) or
+// its window log (bit 1).  Below the capacity limits the buffers grow and
+// the window is redone.  At a limit, under the continue rule, the step size
+// is halved instead (the trajectory does not depend on it: Sec. 4 box, and
+// subsequent steps continue the pending pair, Sec. 5), so the same committed
+// events come out in shorter windows; the tuner's bounds follow, so it does
+// not climb back.  Under the wipe rule the trajectory depends on the step
+// size: there the limit is an error.
+static int on_overflow(sr_sim* s, uint32_t ovf, int64_t span) {
+  Lattice& L = s->L;
+  const bool hist_full = (ovf & 1u) && L.hcap >= (L.Lz > 1 ? kMaxHistCap3 : kMaxHistCap);
+  const bool log_full = (ovf & 2u) && L.wcap >= kMaxWcap;
+  if (!hist_full && !log_full) return grow(s, ovf);
+  if (L.wipe)
+    SR_FAIL(s, SR_EOVERFLOW, "%s capacity limit reached (the wipe-the-slate rule cannot shorten its step)",
+            hist_full ? "boundary list" : "window log");
+  if (span <= 1) SR_FAIL(s, SR_EOVERFLOW, "capacity limit reached by a one-tick window");
+  s->W = std::max<int64_t>(1, span / 2);
+  s->Wmax = std::min(s->Wmax, s->W);
+  s->Wmin = std::min(s->Wmin, s->W);
+  const uint32_t rest = ((ovf & 1u) && !hist_full ? 1u : 0u) | ((ovf & 2u) && !log_full ? 2u : 0u);
+  return rest ? grow(s, rest) : SR_OK;
 }
 
 static int commit(sr_sim* s) {
@@ -606,9 +632,11 @@ static int run_one_window(sr_sim* s, int32_t* g_out) {
       const IterFlags& f = s->hflags[i];
       s->iterations++;
       if (f.ovf_hist || f.ovf_log) {
-        int rc = grow(s, (f.ovf_hist ? 1u : 0u) | (f.ovf_log ? 2u : 0u));
+        int rc = on_overflow(s, (f.ovf_hist ? 1u : 0u) | (f.ovf_log ? 2u : 0u), s->st.t_end - s->st.t_c);
         if (rc != SR_OK) return rc;
-        it = -k;                   // re-run the window from its committed state
+        // re-run the window from its committed state (its step may be shorter)
+        s->st.t_end = std::min(s->st.t_c + s->W, s->H);
+        it = -k;
         break;
       }
       if (!f.changed) {
@@ -1101,9 +1129,9 @@ static int batch_end(BatchLaunch& bl, BatchStage& hs) {
         one = SR_EOVERFLOW;
         s->err = "a boundary list or window log overflowed (growing it needs an allocation)";
       } else {
-        // grow what overflowed, then run this step's windows alone from the
-        // last committed one
-        one = grow(s, bits ? bits : 3u);
+        // grow what overflowed (or shorten the step at a capacity limit),
+        // then run this step's windows alone from the last committed one
+        one = on_overflow(s, bits ? bits : 3u, r.st.t_end - r.st.t_c);
         if (one == SR_OK) one = sr_run_window(s, bl.max_windows > 0 ? bl.max_windows : -1, nullptr, nullptr);
       }
     } else if (r.status == kNoConv) {

@@ -320,3 +320,29 @@ def test_wipe_step_rule_one_launch_per_iteration(monkeypatch):
     p = W.params(Lx, Ly, bx, by, T=T, h=h, window=win, horizon=hor, seed=77,
                  tick_bits=tb, rule=rule, init=init, step="wipe")
     check_against_oracle(p)
+
+
+def test_capacity_limit_shortens_the_step():
+    # 64-wide edges at T = 3.5 over one 40-unit window collect ~1500 boundary
+    # events, beyond the largest list (1024): the window is committed in
+    # shorter steps, with the same events as the oracle (the continue rule's
+    # trajectory does not depend on the step size); the wipe rule, whose
+    # trajectory does, reports the limit
+    sr = _sr()
+    p = W.params(128, 32, 64, 16, T=3.5, h=0.0, window=40.0, horizon=40.0, seed=919, log_mode="digest")
+    s = sr.Sim(p)
+    w0 = s.observables()["window_ticks"]
+    s.run()
+    o = s.observables()
+    ref = oracle.des(p, log=False)
+    assert o["tick"] == o["horizon_ticks"]
+    assert o["window_ticks"] < w0 and o["windows"] >= 2
+    assert np.array_equal(s.spins(), ref["spins"])
+    assert np.array_equal(s.digests()[0], ref["sub_digest"])
+    assert np.array_equal(s.carry(), ref["carry"][:, :3])
+    s.close()
+    s = sr.Sim(dict(p, step="wipe"))
+    with pytest.raises(sr.SRError) as e:
+        s.run()
+    assert e.value.code == sr.SR_EOVERFLOW
+    s.close()
