@@ -57,8 +57,17 @@ def sha_file(path):
         return hashlib.sha256(f.read()).hexdigest()
 
 
+KERNEL_SOURCES = ("sr_kernels.hip", "sr_device.h", "sr_internal.h")
+
+
 def kernel_source_sha():
-    return sha_file(os.path.join(ROOT, "paper_cs_0405053_amd", "csrc", "sr_kernels.hip"))
+    """SHA-256 of the persistent and relaxation kernels' sources (the kernel
+    file, its device helpers and the shared definitions, concatenated)."""
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_cs_0405053_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def profile_record(name):

@@ -178,7 +178,7 @@ enum { kRunning = 0, kDone = 1, kOverflow = 2, kNoConv = 3, kBad = 4, kPaused = 
 // Step size for the next window (Sec. 4 box: a step size is chosen at every
 // step; the trajectory does not depend on it).  Aims at about kTargetG
 // iterations per window, at most halving or doubling per window.
-constexpr int kTargetG = 16;
+constexpr int kTargetG = 12;
 __host__ __device__ inline int64_t tune_window(int64_t W, int g, int64_t Wmin, int64_t Wmax) {
   if (g < 1) g = 1;
   int64_t want = (int64_t)((double)W * kTargetG / g);
