@@ -57,12 +57,13 @@ def sha_file(path):
         return hashlib.sha256(f.read()).hexdigest()
 
 
-KERNEL_SOURCES = ("sr_kernels.hip", "sr_device.h", "sr_internal.h")
+KERNEL_SOURCES = ("sr_kernels.hip", "sr_device.h", "sr_internal.h", "sr_api.hip")
 
 
 def kernel_source_sha():
-    """SHA-256 of the persistent and relaxation kernels' sources (the kernel
-    file, its device helpers and the shared definitions, concatenated)."""
+    """SHA-256 of the persistent and relaxation kernels' sources and of the
+    host code that sizes and launches them (checkpoint interval, tuner,
+    grid), concatenated."""
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_cs_0405053_amd", "csrc", name), "rb") as f:

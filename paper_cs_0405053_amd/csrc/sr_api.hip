@@ -272,17 +272,16 @@ static void free_all(sr_sim* s) {
 // standard deviations, boundary lists in steps of 32 entries (a relaxation
 // wave holds 12 of them in LDS: 3 KB at 32, which lets more waves of the
 // persistent kernel share a CU; an overflow re-runs the window with double
-// capacity and the same result).  Checkpoints every kCkIntPlain events or break points
-// (the persistent kernel uses kCkIntBatch: its tasks wait for their stores at
-// the release, so fewer checkpoints pay there), up to 32 per run, enough for
-// 1.5 x the largest expected count.
+// capacity and the same result).  Checkpoints every kCkInt events or break
+// points, up to 32 per run, enough for 1.5 x the largest expected count.
 struct Plan {
   int hcap, wcap, ckint, nck;
   size_t bytes;
 };
-// Items between checkpoints (measured: the 1024x1024 workload is fastest
-// at 4 on the plain path, the 512-lattice batch at 8 in the persistent kernel).
-constexpr int kCkIntPlain = 4, kCkIntBatch = 8;
+// Items between checkpoints (measured: 4 is fastest for the 1024x1024
+// workload on the plain path and for the 512-lattice batch in the persistent
+// kernel: 2.00 s per launch against 2.02 / 2.06 / 2.12 s at 8 / 12 / 16).
+constexpr int kCkInt = 4;
 static Plan plan(const sr_params& p, int64_t Wmax) {
   Plan pl;
   const bool d3 = is3d(p);
@@ -295,7 +294,7 @@ static Plan plan(const sr_params& p, int64_t Wmax) {
   pl.wcap = (int)std::max(64.0, std::ceil((blk + 6.0 * std::sqrt(blk) + 32.0) / 64.0) * 64.0);
   if (p.hist_cap > 0) pl.hcap = p.hist_cap;
   if (p.wlog_cap > 0) pl.wcap = p.wlog_cap;
-  pl.ckint = kCkIntPlain;
+  pl.ckint = kCkInt;
   // (3D runs always start at the window start: one unused checkpoint slot)
   pl.nck = d3 ? 1 : (int)std::min(32.0, std::max(4.0, std::ceil(1.5 * blk / pl.ckint) + 1.0));
   size_t nsub = (size_t)(p.Lx / p.bx) * (p.Ly / p.by) * (Lz / bz), nsite = (size_t)p.Lx * p.Ly * Lz;
@@ -1041,7 +1040,6 @@ static int batch_begin(sr_sim* const* sims, int32_t n, int32_t max_windows, hipS
     sr_sim* s = sims[hs.idx[k]];
     hs.lat[k] = s->L;
     hs.lat[k].need = s->need;
-    hs.lat[k].ckint = kCkIntBatch;
     if (hipMemsetAsync(s->need, 0, 2 * (size_t)need_stride(s->L.nsub), stream) != hipSuccess) {
       release();
       SR_FAIL(s0, SR_EDEVICE, "clearing run marks failed");
