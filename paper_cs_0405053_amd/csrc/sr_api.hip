@@ -1040,7 +1040,9 @@ static int batch_begin(sr_sim* const* sims, int32_t n, int32_t max_windows, hipS
     sr_sim* s = sims[hs.idx[k]];
     hs.lat[k] = s->L;
     hs.lat[k].need = s->need;
-    if (hipMemsetAsync(s->need, 0, 2 * (size_t)need_stride(s->L.nsub), stream) != hipSuccess) {
+    // (a kernel, not a memset: callers of the no-allocation form may be
+    // capturing the stream into a graph)
+    if (launch_zero(s->need, 2 * (size_t)need_stride(s->L.nsub), stream) != hipSuccess) {
       release();
       SR_FAIL(s0, SR_EDEVICE, "clearing run marks failed");
     }

@@ -1100,12 +1100,10 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t stream) {
   return hipGetLastError();
 }
 
-// The compile-time 16x16 body needs 116 VGPRs inside the task loop: capped at
-// four waves per SIMD it runs without spills.  Measured on the 512-lattice
-// batch and three 1024x1024 lattices (flips/s): runtime shape at 6 / 7 / 8
-// waves per SIMD 8.20e7 / 8.19e7 / 7.68e7 and 5.74e7 / 5.51e7 / 5.25e7
-// (more waves, more spills); 16x16 at 4 / 5 / 6 waves 8.10e7 / 8.22e7 /
-// 7.87e7 and 6.31e7 / 6.17e7 / 6.15e7.
+// Both instantiations run six waves per SIMD (80 VGPRs).  The 16x16 body
+// would take 118 without the cap; capped, its spills are reloaded once per
+// task, outside the event loop, and it is faster than at four waves without
+// spills (512-lattice batch 2.93 s against 3.45 s per launch).
 static const void* batch_kernel_for(int shape) {
   return shape == kBatch16NoWrap ? (const void*)batch_kernel<16, 16, true, 6> : (const void*)batch_kernel<0, 0, false, 6>;
 }
