@@ -341,6 +341,15 @@ def test_capacity_limit_shortens_the_step():
     assert np.array_equal(s.digests()[0], ref["sub_digest"])
     assert np.array_equal(s.carry(), ref["carry"][:, :3])
     s.close()
+    # the batched form: the overflowing lattice is finished by the plain path
+    # with the shorter step
+    s = sr.Sim(p)
+    sr.batch_run([s])
+    o = s.observables()
+    assert o["tick"] == o["horizon_ticks"] and o["window_ticks"] < w0
+    assert np.array_equal(s.spins(), ref["spins"])
+    assert np.array_equal(s.digests()[0], ref["sub_digest"])
+    s.close()
     s = sr.Sim(dict(p, step="wipe"))
     with pytest.raises(sr.SRError) as e:
         s.run()
