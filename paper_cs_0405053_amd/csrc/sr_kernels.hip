@@ -64,6 +64,18 @@ constexpr int lane_shift(int nblk) {
 // point where every XCD's reads meet, so the task publishes by waiting for
 // its stores, with no L2 write-back); else an ordinary store (the plain
 // kernels publish at the kernel boundary).
+// A load of data other waves wrote in this launch.  COH: device-coherent
+// (past this CU's L1, at the point device-coherent stores reach), so no
+// acquire is needed before it; else an ordinary load.
+template <bool COH, class T>
+__device__ __forceinline__ T gget(const T* p) {
+  if constexpr (COH) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    return *p;
+  }
+}
+
 template <bool COH, class T, class U>
 __device__ __forceinline__ void gput(T* p, U v) {
   if constexpr (COH) {
@@ -94,7 +106,7 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
   const int de = cy * nbx + (cx + 1) % nbx;
   const uint8_t* slot_prev = slot_at(L, (st.it + 1) & 1);
   const uint8_t* chg_prev = chg_at(L, (st.it + 1) & 1);
-  const int sprev = first ? 0 : slot_prev[d];
+  const int sprev = first ? 0 : gget<COH>(&slot_prev[d]);
   const int sout = first ? 0 : 1 - sprev;
   const Carry* cin = &carry_at(L, st.wp)[d];
   const uint32_t k0 = L.seed_lo, k1 = L.seed_hi;
@@ -111,17 +123,17 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
   if (!first) {
     int64_t tau = kTickInf;
     auto edge_change = [&](int e, int edge, bool none) {
-      if (none || !(chg_prev[e] & (1u << edge))) return;
-      int64_t f = fct_at(L, slot_prev[e])[e * kEdges + edge];
+      if (none || !(gget<COH>(&chg_prev[e]) & (1u << edge))) return;
+      int64_t f = gget<COH>(&fct_at(L, gget<COH>(&slot_prev[e]))[e * kEdges + edge]);
       tau = f < tau ? f : tau;
     };
     edge_change(dn, kS, wrapy);
     edge_change(ds, kN, wrapy);
     edge_change(dw, kE, wrapx);
     edge_change(de, kW, wrapx);
-    const int nck = (int)L.ckn[d];
+    const int nck = (int)gget<COH>(&L.ckn[d]);
     const Ckpt* cks = L.ck + (size_t)d * L.nck;
-    bool ok = lane < nck && (int64_t)cks[lane < nck ? lane : 0].meta[kCkT] <= tau;
+    bool ok = lane < nck && (int64_t)gget<COH>(&cks[lane < nck ? lane : 0].meta[kCkT]) <= tau;
     uint64_t m = ballot(ok);
     if (m) ck = 63 - __builtin_clzll(m);
   }
@@ -132,8 +144,8 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
   int nev, nbound, n0[4], h0;
   if (ck >= 0) {
     const Ckpt* c = L.ck + (size_t)d * L.nck + ck;
-    cls = c->cls[lane];
-    const uint64_t mw = lane < kCkWords ? c->meta[lane] : 0ull;
+    cls = gget<COH>(&c->cls[lane]);
+    const uint64_t mw = lane < kCkWords ? gget<COH>(&c->meta[lane]) : 0ull;
     const uint64_t pair = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(mw >> 32), lane >> 1, 64) << 32) |
                           (uint32_t)__shfl((int)(uint32_t)mw, lane >> 1, 64);
     ncnt = lane < kClasses ? (uint32_t)(pair >> (32 * (lane & 1))) : 0u;
@@ -156,7 +168,7 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
       int gy = y0 + ty - 1, gx = x0 + tx - 1;
       gy = gy < 0 ? gy + L.Ly : (gy >= L.Ly ? gy - L.Ly : gy);
       gx = gx < 0 ? gx + L.Lx : (gx >= L.Lx ? gx - L.Lx : gx);
-      tile[i] = sp[(int64_t)gy * L.Lx + gx];
+      tile[i] = gget<COH>(&sp[(int64_t)gy * L.Lx + gx]);
     }
     __syncthreads();
     // classes of owned sites, 4 bits each; unused nibbles hold 0xF
@@ -185,7 +197,7 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
       uint32_t tot = rdl(wave_incl_scan(c), 63);
       if (lane == k) ncnt = tot;
     }
-    j = cin->j; acc = cin->acc; anchor = cin->anchor; dtot = 0;
+    j = gget<COH>(&cin->j); acc = gget<COH>(&cin->acc); anchor = gget<COH>(&cin->anchor); dtot = 0;
     if (L.wipe && st.t_c > 0) {
       // wipe the slate (Sec. 5): the pending pair is dropped, the next one
       // starts its hazard at the window start
@@ -217,33 +229,33 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
     const bool none[4] = {first || wrapy, first || wrapy, first || wrapx, first || wrapx};
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      int sl = none[q] ? 0 : slot_prev[ev[q]];
+      int sl = none[q] ? 0 : gget<COH>(&slot_prev[ev[q]]);
       li[q] = hist_at(L, sl) + ((size_t)ev[q] * kEdges + ed[q]) * hcap;
-      ni[q] = none[q] ? 0 : clampn(hcnt_at(L, sl)[ev[q] * kEdges + ed[q]]);
+      ni[q] = none[q] ? 0 : clampn(gget<COH>(&hcnt_at(L, sl)[ev[q] * kEdges + ed[q]]));
     }
   }
   const uint64_t* pb = hist_at(L, sprev) + (size_t)d * kEdges * hcap;
   int np[4];
 #pragma unroll
-  for (int e = 0; e < 4; ++e) np[e] = first ? 0 : clampn(hcnt_at(L, sprev)[d * kEdges + e]);
+  for (int e = 0; e < 4; ++e) np[e] = first ? 0 : clampn(gget<COH>(&hcnt_at(L, sprev)[d * kEdges + e]));
   const int o1 = ni[0], o2 = o1 + ni[1], o3 = o2 + ni[2], tot = o3 + ni[3];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int oq = q == 0 ? 0 : q == 1 ? o1 : q == 2 ? o2 : o3;
     for (int i = lane; i < ni[q]; i += 64) {
-      uint64_t x = li[q][i];
+      uint64_t x = gget<COH>(&li[q][i]);
       raw[oq + i] = ((x >> kPosBits) << kKeyShift) | ((uint64_t)q << 16) | (x & 0xFFFF);
     }
   }
 #pragma unroll
   for (int e = 0; e < 4; ++e)
-    for (int i = lane; i < np[e]; i += 64) lprev[e * hcap + i] = pb[e * hcap + i];
+    for (int i = lane; i < np[e]; i += 64) lprev[e * hcap + i] = gget<COH>(&pb[e * hcap + i]);
   // committed digest and flip count of this subdomain, needed at the end;
   // the largest boundary-event count of its earlier runs in this window
-  const uint64_t dig_in = rdl64(cin->digest, 0);
-  const int64_t flips_in = (int64_t)rdl64((uint64_t)cin->flips, 0);
-  const int64_t nbmax_in = first ? 0 : (int64_t)rdl64((uint64_t)carry_at(L, st.wp ^ 1)[d].nbmax, 0);
-  const unsigned long long ev_in = rdl64(L.stat[d].events, 0), runs_in = rdl64(L.stat[d].runs, 0);
+  const uint64_t dig_in = rdl64(gget<COH>(&cin->digest), 0);
+  const int64_t flips_in = (int64_t)rdl64((uint64_t)gget<COH>(&cin->flips), 0);
+  const int64_t nbmax_in = first ? 0 : (int64_t)rdl64((uint64_t)gget<COH>(&carry_at(L, st.wp ^ 1)[d].nbmax), 0);
+  const unsigned long long ev_in = rdl64(gget<COH>(&L.stat[d].events), 0), runs_in = rdl64(gget<COH>(&L.stat[d].runs), 0);
   __syncthreads();
   if (tot > 0) {
     for (int i = lane; i < tot; i += 64) {
@@ -289,7 +301,7 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
   uint64_t lbuf = 0;
   {
     int b = nev & ~63;
-    if (b + lane < nev && b + lane < wcap) lbuf = wl[b + lane];
+    if (b + lane < nev && b + lane < wcap) lbuf = gget<COH>(&wl[b + lane]);
   }
   auto log_flush = [&](int k) {          // k buffered entries in lanes 0..k-1
     int at = nev - k + lane;
@@ -652,7 +664,7 @@ struct RunView {
 };
 __device__ __forceinline__ RunView load_run(const LatRun* run, int lane) {
   RunView v;
-  v.w = lane < 32 ? reinterpret_cast<const uint32_t*>(run)[lane] : 0u;
+  v.w = lane < 32 ? gget<true>(&reinterpret_cast<const uint32_t*>(run)[lane]) : 0u;
   return v;
 }
 __device__ __forceinline__ Step step_of(const RunView& v) {
@@ -675,18 +687,25 @@ __device__ __forceinline__ Step step_of(const RunView& v) {
 // Ordering between the tasks of one lattice.  Everything the batched form
 // writes for other waves (a run's results, the decider's run record, slot
 // and change arrays, counts) goes out with device-coherent stores, written
-// through to the point where every XCD's reads meet: publishing then only
-// waits for those stores, with no L2 write-back.  (A device-scope release
-// writes the whole L2 back and the L2 serialises it: issued once per task,
-// it took over half of the batched form's time.)  A task starts with the
-// device-scope acquire, which invalidates this CU's L1 and the L2's copies
-// of lines other XCDs wrote (the workgroup-scope L1 invalidate is not
-// enough: outside threadgroup-split mode it left stale L1 lines visible to
-// the next task, measured as wrong trajectories).
+// through to the point where every XCD's reads meet, and everything it reads
+// that other waves wrote in this launch comes in with device-coherent loads
+// (past this CU's L1; the compiled kernel has no other vector load).  So
+// publishing is a wait for the stores, and a task needs no acquire: its
+// loads are issued after the queue slot that named the task was read, and
+// that slot was written after the producer's stores completed.  (Measured
+// alternatives: a device-scope release per task writes the whole L2 back and
+// the L2 serialises it, over half of the batched form's time; a device-scope
+// acquire per task drops the L2's copies of other XCDs' lines; the
+// workgroup-scope L1 invalidate left stale L1 lines outside threadgroup-split
+// mode, seen as wrong trajectories.)
 __device__ __forceinline__ void publish_wait() { __asm__ volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory"); }
-__device__ __forceinline__ void lattice_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 
-// Device-coherent copy of 16 bytes (two 8-byte stores).
+// Device-coherent load and store of 16 bytes (two 8-byte accesses).
+__device__ __forceinline__ uint4 gget16(const uint4* p) {
+  const unsigned long long* q = reinterpret_cast<const unsigned long long*>(p);
+  const unsigned long long a = gget<true>(q), b = gget<true>(q + 1);
+  return make_uint4((uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32));
+}
 __device__ __forceinline__ void gput16(uint4* p, const uint4& v) {
   unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
   gput<true>(q, ((unsigned long long)v.y << 32) | v.x);
@@ -707,16 +726,14 @@ __device__ uint32_t enqueue_iteration(const BatchArgs& B, int lat, LatRun* run, 
     }
     // the four 16-byte loads in flight together (one round trip on the
     // decider's path instead of four)
-    const uint4* p = reinterpret_cast<const uint4*>(nb + (size_t)w * 64);
-    uint4 xs[4];
+    const unsigned long long* p = reinterpret_cast<const unsigned long long*>(nb + (size_t)w * 64);
+    unsigned long long xs[8];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) xs[k] = p[k];
+    for (int k = 0; k < 8; ++k) xs[k] = gget<true>(&p[k]);
     unsigned long long m = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const uint4 x = xs[k];
-      const unsigned long long lo = ((unsigned long long)x.y << 32) | x.x;
-      const unsigned long long hi = ((unsigned long long)x.w << 32) | x.z;
+      const unsigned long long lo = xs[2 * k], hi = xs[2 * k + 1];
       m |= (((lo & 0x0101010101010101ull) * 0x0102040810204080ull) >> 56) << (16 * k);
       m |= (((hi & 0x0101010101010101ull) * 0x0102040810204080ull) >> 56) << (16 * k + 8);
     }
@@ -732,7 +749,7 @@ __device__ uint32_t enqueue_iteration(const BatchArgs& B, int lat, LatRun* run, 
     const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll 4
     for (int i = lane; i < n16; i += 64) {
-      gput16(&sn[i], sp[i]);
+      gput16(&sn[i], gget16(&sp[i]));
       gput16(&cn[i], zero);
     }
   }
@@ -755,7 +772,7 @@ __device__ uint32_t enqueue_iteration(const BatchArgs& B, int lat, LatRun* run, 
   if (lane < kShards) gput<true>(&B.rem[(size_t)lat * kShards + lane].n, (int32_t)ns);
   if (lane == 0) {
     gput<true>(&run->shards_left, (int32_t)(count < (uint32_t)kShards ? count : (uint32_t)kShards));
-    gput<true>(&run->tasks, run->tasks + count);
+    gput<true>(&run->tasks, gget<true>(&run->tasks) + count);
   }
   publish_wait();
   unsigned long long sbase = 0;
@@ -817,7 +834,6 @@ __device__ __forceinline__ void put_step(Step* p, const Step& st) {
 // window (committed time advances), or completion.
 __device__ void decide(const BatchArgs& B, int lat, int lane) {
   CLattice& L = ((CLattice*)B.lat)[lat];
-  lattice_acquire();
   LatRun* run = &B.run[lat];
   const RunView rv = load_run(run, lane);
   IterFlags f;
@@ -968,7 +984,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     const uint32_t pay = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
     const int lat = (int)((pay >> 20) & 0xFFF);
     const int d = (int)(pay & 0xFFFFF);
-    lattice_acquire();
     LatRun* run = &B.run[lat];
     const Step st = step_of(load_run(run, lane));
     relax_subdomain<BX, BY, NW, true>(lats[lat], st, d, tile, &run->fl);
