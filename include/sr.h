@@ -266,7 +266,8 @@ int sr_batch_step_static(sr_sim* const* sims, int32_t n, int32_t max_windows, vo
  * (bz = bx), 8^3 halved until it divides every side.  A simulation created with window = 0 then
  * adapts its step size after every committed window from the measured
  * iterations g (Sec. 4 box: a step size is chosen at each step), aiming at
- * about 12 iterations per window; the trajectory does not depend on it. */
+ * about 12 iterations per window in sr_run_window and 6 in the batched form
+ * (whose per-window cost is lower); the trajectory does not depend on it. */
 int sr_tune(const sr_params* p, int32_t* bx, int32_t* by, double* window);
 
 /* ---- serving: continuous batching of simulation requests ----

@@ -645,7 +645,7 @@ static int run_one_window(sr_sim* s, int32_t* g_out) {
         // queue about as many iterations as the last window needed
         s->batch_hint = std::max(2, std::min(kMaxBatch, g + 1));
         int rc = commit(s);
-        if (s->tune) s->W = tune_window(s->W, g, s->Wmin, s->Wmax);
+        if (s->tune) s->W = tune_window(s->W, g, s->Wmin, s->Wmax, kTargetGPlain);
         return rc;
       }
     }

@@ -176,12 +176,18 @@ struct LatRun {
 enum { kRunning = 0, kDone = 1, kOverflow = 2, kNoConv = 3, kBad = 4, kPaused = 5 };
 
 // Step size for the next window (Sec. 4 box: a step size is chosen at every
-// step; the trajectory does not depend on it).  Aims at about kTargetG
-// iterations per window, at most halving or doubling per window.
-constexpr int kTargetG = 12;
-__host__ __device__ inline int64_t tune_window(int64_t W, int g, int64_t Wmin, int64_t Wmax) {
+// step; the trajectory does not depend on it).  Aims at about `target`
+// iterations per window, at most halving or doubling per window.  Shorter
+// windows re-simulate less but pay the per-window cost more often, and that
+// cost differs by executor: the plain form's host loop waits for every
+// window, the persistent kernel's decider starts the next one on the device.
+// Measured best on the 512-lattice batch: plain 12 (8 streams 16.7 s against
+// 20.6 s at 6), persistent 6 (1.43 s per launch against 1.45 / 1.58 / 1.75 /
+// 1.53 s at 8 / 10 / 12 / 5).
+constexpr int kTargetGPlain = 12, kTargetGBatch = 6;
+__host__ __device__ inline int64_t tune_window(int64_t W, int g, int64_t Wmin, int64_t Wmax, int target) {
   if (g < 1) g = 1;
-  int64_t want = (int64_t)((double)W * kTargetG / g);
+  int64_t want = (int64_t)((double)W * target / g);
   int64_t nw = (W + want) / 2;                 // damped
   if (nw < W / 2) nw = W / 2;
   if (nw > 2 * W) nw = 2 * W;

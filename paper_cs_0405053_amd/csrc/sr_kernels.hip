@@ -870,7 +870,7 @@ __device__ void decide(const BatchArgs& B, int lat, int lane) {
     }
     int64_t W = rv.i64(offsetof(LatRun, W));
     if (tune) {
-      W = tune_window(W, st.it + 1, rv.i64(offsetof(LatRun, Wmin)), rv.i64(offsetof(LatRun, Wmax)));
+      W = tune_window(W, st.it + 1, rv.i64(offsetof(LatRun, Wmin)), rv.i64(offsetof(LatRun, Wmax)), kTargetGBatch);
       if (lane == 0) gput<true>(&run->W, W);
     }
     if (st.t_c >= H) {

@@ -257,7 +257,7 @@ hipError_t launch_batch(const BatchArgs& B, int, int, size_t, hipStream_t) {
       r.windows++;
       r.iterations += G;
       r.last_g = G;
-      if (r.tune) r.W = tune_window(r.W, G, r.Wmin, r.Wmax);
+      if (r.tune) r.W = tune_window(r.W, G, r.Wmin, r.Wmax, kTargetGBatch);
       if (r.st.t_c >= r.H) { r.status = kDone; break; }
       r.st.t_end = r.st.t_c + r.W < r.H ? r.st.t_c + r.W : r.H;
       if (budget > 0 && --budget == 0) r.status = kPaused;
