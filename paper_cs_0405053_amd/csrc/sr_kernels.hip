@@ -188,14 +188,21 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
     hS = ballot(lane < bx && tile[(by + 1) * tw + lane + 1] > 0);
     hW = ballot(lane < by && tile[(lane + 1) * tw] > 0);
     hE = ballot(lane < by && tile[(lane + 1) * tw + bx + 1] > 0);
-    // class counts N_k in lane k
-    ncnt = 0;
-    for (int k = 0; k < kClasses; ++k) {
-      uint64_t x = cls ^ (0x1111111111111111ull * (uint64_t)k);
-      uint64_t nz = (x | (x >> 1) | (x >> 2) | (x >> 3)) & 0x1111111111111111ull;
-      uint32_t c = (uint32_t)__popcll(~nz & 0x1111111111111111ull);
-      uint32_t tot = rdl(wave_incl_scan(c), 63);
-      if (lane == k) ncnt = tot;
+    // class counts N_k in lane k: each lane counts its own sites per class
+    // in 12-bit fields (at most 1024 sites in a block), classes 0..4 in one
+    // word and 5..9 in another, and two wave sums add the lanes up (unused
+    // nibbles hold 0xF and count nowhere)
+    {
+      uint64_t p0 = 0, p1 = 0;
+      for (int i = 0; i < S; ++i) {
+        const uint32_t k = (uint32_t)(cls >> (4 * i)) & 15u;
+        p0 += k < 5 ? 1ull << (12 * k) : 0ull;
+        p1 += k - 5u < 5u ? 1ull << (12 * (k - 5u)) : 0ull;
+      }
+      p0 = wave_sum64(p0);
+      p1 = wave_sum64(p1);
+      const uint64_t pk = lane < 5 ? p0 >> (12 * lane) : p1 >> (12 * (lane - 5));
+      ncnt = lane < kClasses ? (uint32_t)(pk & 0xFFF) : 0u;
     }
     j = gget<COH>(&cin->j); acc = gget<COH>(&cin->acc); anchor = gget<COH>(&cin->anchor); dtot = 0;
     if (L.wipe && st.t_c > 0) {
