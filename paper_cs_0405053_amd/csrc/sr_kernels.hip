@@ -33,6 +33,9 @@ namespace sr {
 // (whichever is larger): the four raw neighbour lists (reused for the own
 // lists of the run once merged), the merged stream, and the four own lists of
 // the previous iteration, up to hcap entries each.
+// Bytes of the committed block each lane loads per round (all in flight).
+constexpr int kTileStage = 8;
+
 __host__ __device__ inline size_t relax_lds_bytes(int bx, int by, int hcap) {
   size_t tile = (size_t)(bx + 2) * (by + 2);
   size_t lists = (size_t)3 * 4 * hcap * sizeof(uint64_t);
@@ -90,7 +93,11 @@ template <int BX, int BY, bool NW = false, bool COH = false, class LT>
 __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int d,
                                                 int8_t* lds, IterFlags* fl) {
   static_assert((BX == 0) == (BY == 0), "both or neither block sides fixed");
-  const int lane = lane_id();
+  // the lane index, opaque to the compiler: per-lane offsets are then
+  // computed in each run, not hoisted out of the persistent kernel's task
+  // loop and kept in spilled registers
+  int lane = lane_id();
+  __asm__ volatile("" : "+v"(lane));
   const int bx = BX ? BX : L.bx, by = BY ? BY : L.by;
   const int sh = BX ? lane_shift(BX * BY) : L.sshift, S = 1 << sh;
   const int nbx = L.nbx, nby = L.nby;
@@ -106,8 +113,6 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
   const int de = cy * nbx + (cx + 1) % nbx;
   const uint8_t* slot_prev = slot_at(L, (st.it + 1) & 1);
   const uint8_t* chg_prev = chg_at(L, (st.it + 1) & 1);
-  const int sprev = first ? 0 : gget<COH>(&slot_prev[d]);
-  const int sout = first ? 0 : 1 - sprev;
   const Carry* cin = &carry_at(L, st.wp)[d];
   const uint32_t k0 = L.seed_lo, k1 = L.seed_hi;
   auto clampn = [&](uint32_t n) { return (int)(n < (uint32_t)hcap ? n : (uint32_t)hcap); };
@@ -117,35 +122,123 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
   for (int k = 0; k < kClasses; ++k)
     if (lane == k) rate = L.rate[k];
 
-  // ---- where to start: the latest checkpoint of this subdomain's last run
-  // whose state only depends on input entries that did not change
+  // ---- setup loads in three dependent rounds, each a gather with one lane
+  // per value (a run then waits for three memory round trips, not one per
+  // value): (1) the slot and change bytes of this subdomain and of its four
+  // neighbours, its checkpoint count and ticks, its carry and work counters;
+  // (2) the facing lists' first-change ticks and lengths and its own lists'
+  // lengths, which pick the checkpoint to resume from (the latest one whose
+  // state only depends on input entries that did not change); (3) that
+  // checkpoint or the committed block, and the list entries.
+  const int ev[4] = {dn, ds, dw, de};
+  const int ed[4] = {kS, kN, kE, kW};      // the neighbour's edge facing us
+  const bool none[4] = {first || wrapy, first || wrapy, first || wrapx, first || wrapx};
+  const Ckpt* cks = L.ck + (size_t)d * L.nck;
+  uint32_t g8 = 0;                         // lane 0: own slot; 1..4: facing slots; 5..8: their change masks
+  uint32_t nck_v = 0;
+  uint64_t ckt = 0, ckv = 0;               // lane k < nck: tick and window event count of checkpoint k
+  if (!first) {
+    const int ql = (lane - 1) & 3;
+    const int el = lane == 0 ? d : ql == 0 ? dn : ql == 1 ? ds : ql == 2 ? dw : de;
+    if (lane < 9) g8 = gget<COH>((lane < 5 ? slot_prev : chg_prev) + el);
+    nck_v = gget<COH>(&L.ckn[d]);
+    if (lane < L.nck) {
+      ckt = gget<COH>(&cks[lane].meta[kCkT]);
+      ckv = gget<COH>(&cks[lane].meta[kCkNev]);
+    }
+  }
+  // lanes 0..4: j, anchor, acc, digest, flips of the committed carry; 5: the
+  // largest boundary-event count of this window's earlier runs; 6, 7: work
+  // counters
+  uint64_t cv = 0;
+  if (lane < 8 && (lane != 5 || !first)) {
+    const uint64_t* cp = lane < 5 ? reinterpret_cast<const uint64_t*>(cin) + lane
+                         : lane == 5 ? reinterpret_cast<const uint64_t*>(&carry_at(L, st.wp ^ 1)[d].nbmax)
+                                     : reinterpret_cast<const uint64_t*>(&L.stat[d]) + (lane - 6);
+    cv = gget<COH>(cp);
+  }
+
+  int sprev = 0, sl[4] = {0, 0, 0, 0}, ni[4] = {0, 0, 0, 0}, np[4] = {0, 0, 0, 0};
   int ck = -1;
   if (!first) {
+    sprev = (int)rdl(g8, 0);
+    uint32_t cm[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      sl[q] = none[q] ? 0 : (int)rdl(g8, 1 + q);
+      cm[q] = rdl(g8, 5 + q);
+    }
+    // lanes 0..3: facing list q's first-change tick (if it changed) and
+    // length; lanes 4..7: own list e's length in the previous run
+    const int ql = lane & 3;
+    const int eq = ql == 0 ? dn : ql == 1 ? ds : ql == 2 ? dw : de;
+    const int edq = ql == 0 ? kS : ql == 1 ? kN : ql == 2 ? kE : kW;
+    const int slq = ql == 0 ? sl[0] : ql == 1 ? sl[1] : ql == 2 ? sl[2] : sl[3];
+    const uint32_t cmq = ql == 0 ? cm[0] : ql == 1 ? cm[1] : ql == 2 ? cm[2] : cm[3];
+    const bool nq = ql < 2 ? wrapy : wrapx;
+    uint64_t f = (uint64_t)kTickInf;
+    uint32_t hc = 0;
+    if (lane < 4) {
+      if (!nq) {
+        if ((cmq >> edq) & 1u) f = (uint64_t)gget<COH>(&fct_at(L, slq)[eq * kEdges + edq]);
+        hc = gget<COH>(&hcnt_at(L, slq)[eq * kEdges + edq]);
+      }
+    } else if (lane < 8) {
+      hc = gget<COH>(&hcnt_at(L, sprev)[d * kEdges + (lane - 4)]);
+    }
     int64_t tau = kTickInf;
-    auto edge_change = [&](int e, int edge, bool none) {
-      if (none || !(gget<COH>(&chg_prev[e]) & (1u << edge))) return;
-      int64_t f = gget<COH>(&fct_at(L, gget<COH>(&slot_prev[e]))[e * kEdges + edge]);
-      tau = f < tau ? f : tau;
-    };
-    edge_change(dn, kS, wrapy);
-    edge_change(ds, kN, wrapy);
-    edge_change(dw, kE, wrapx);
-    edge_change(de, kW, wrapx);
-    const int nck = (int)gget<COH>(&L.ckn[d]);
-    const Ckpt* cks = L.ck + (size_t)d * L.nck;
-    bool ok = lane < nck && (int64_t)gget<COH>(&cks[lane < nck ? lane : 0].meta[kCkT]) <= tau;
-    uint64_t m = ballot(ok);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t fq = (int64_t)rdl64(f, q);
+      tau = fq < tau ? fq : tau;
+      ni[q] = clampn(rdl(hc, q));
+      np[q] = clampn(rdl(hc, 4 + q));
+    }
+    const uint64_t m = ballot(lane < (int)nck_v && (int64_t)ckt <= tau);
     if (m) ck = 63 - __builtin_clzll(m);
   }
+  const int sout = first ? 0 : 1 - sprev;
+
+  // neighbour histories of the previous iteration (break points), each in
+  // the slot its owner last wrote, and this subdomain's own lists of its
+  // previous run; the first iteration assumes none (canonical assumption).
+  // The first 64 entries of each concatenation are gathered now, beside the
+  // checkpoint or block loads, and go to LDS once the tile's LDS is free.
+  const int o1 = ni[0], o2 = o1 + ni[1], o3 = o2 + ni[2], tot = o3 + ni[3];
+  const int p1 = np[0], p2 = p1 + np[1], p3 = p2 + np[2], totp = p3 + np[3];
+  const uint64_t* pb = hist_at(L, sprev) + (size_t)d * kEdges * hcap;
+  auto nb_src = [&](int i, int& q, int& k) -> const uint64_t* {
+    q = i < o1 ? 0 : i < o2 ? 1 : i < o3 ? 2 : 3;
+    k = i - (q == 0 ? 0 : q == 1 ? o1 : q == 2 ? o2 : o3);
+    const int e = q == 0 ? dn : q == 1 ? ds : q == 2 ? dw : de;
+    const int eg = q == 0 ? kS : q == 1 ? kN : q == 2 ? kE : kW;
+    const int s = q == 0 ? sl[0] : q == 1 ? sl[1] : q == 2 ? sl[2] : sl[3];
+    return hist_at(L, s) + ((size_t)e * kEdges + eg) * hcap + k;
+  };
+  auto own_at = [&](int i) -> int {       // offset of own entry i in the per-edge layout
+    const int e = i < p1 ? 0 : i < p2 ? 1 : i < p3 ? 2 : 3;
+    return e * hcap + i - (e == 0 ? 0 : e == 1 ? p1 : e == 2 ? p2 : p3);
+  };
+  uint64_t xn = 0, xo = 0;
+  if (lane < tot) { int q, k; xn = gget<COH>(nb_src(lane, q, k)); }
+  if (lane < totp) xo = gget<COH>(&pb[own_at(lane)]);
 
   uint64_t cls, hN, hS, hW, hE, j, acc, dtot;
   uint32_t ncnt;
   int64_t anchor;
   int nev, nbound, n0[4], h0;
+  uint64_t lbuf = 0;                       // window log entries of the unfinished 64-chunk
+  uint64_t* wl = L.wlog + (size_t)d * L.wcap;
+  const int wcap = L.wcap;
   if (ck >= 0) {
-    const Ckpt* c = L.ck + (size_t)d * L.nck + ck;
+    const Ckpt* c = cks + ck;
     cls = gget<COH>(&c->cls[lane]);
     const uint64_t mw = lane < kCkWords ? gget<COH>(&c->meta[lane]) : 0ull;
+    {
+      const int nv = (int)rdl64(ckv, ck) & ~63;
+      const int nevc = (int)(uint32_t)rdl64(ckv, ck);
+      if (nv + lane < nevc && nv + lane < wcap) lbuf = gget<COH>(&wl[nv + lane]);
+    }
     const uint64_t pair = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(mw >> 32), lane >> 1, 64) << 32) |
                           (uint32_t)__shfl((int)(uint32_t)mw, lane >> 1, 64);
     ncnt = lane < kClasses ? (uint32_t)(pair >> (32 * (lane & 1))) : 0u;
@@ -159,16 +252,31 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
     h0 = (int)rdl(mw, kCkHead);
   } else {
     // committed block + one-site halo -> LDS (internal wrap falls out of the
-    // periodic global index when the block spans the torus)
+    // periodic global index when the block spans the torus), loaded in
+    // stages of kTileStage bytes per lane, all in flight together
     int8_t* tile = lds;
     const int8_t* sp = spins_at(L, st.wp);
-    const int tw = bx + 2;
-    for (int i = lane; i < (by + 2) * tw; i += 64) {
-      int ty = i / tw, tx = i - ty * tw;
-      int gy = y0 + ty - 1, gx = x0 + tx - 1;
-      gy = gy < 0 ? gy + L.Ly : (gy >= L.Ly ? gy - L.Ly : gy);
-      gx = gx < 0 ? gx + L.Lx : (gx >= L.Lx ? gx - L.Lx : gx);
-      tile[i] = gget<COH>(&sp[(int64_t)gy * L.Lx + gx]);
+    const int tw = bx + 2, ntile = (by + 2) * tw;
+    const int ln = lane;
+    for (int b0 = 0; b0 < ntile; b0 += 64 * kTileStage) {
+      int8_t tv[kTileStage];
+#pragma unroll
+      for (int k = 0; k < kTileStage; ++k) {
+        const int i = b0 + 64 * k + ln;
+        tv[k] = 0;
+        if (i < ntile) {
+          const int ty = i / tw, tx = i - ty * tw;
+          int gy = y0 + ty - 1, gx = x0 + tx - 1;
+          gy = gy < 0 ? gy + L.Ly : (gy >= L.Ly ? gy - L.Ly : gy);
+          gx = gx < 0 ? gx + L.Lx : (gx >= L.Lx ? gx - L.Lx : gx);
+          tv[k] = gget<COH>(&sp[(int64_t)gy * L.Lx + gx]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kTileStage; ++k) {
+        const int i = b0 + 64 * k + ln;
+        if (i < ntile) tile[i] = tv[k];
+      }
     }
     __syncthreads();
     // classes of owned sites, 4 bits each; unused nibbles hold 0xF
@@ -204,7 +312,7 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
       const uint64_t pk = lane < 5 ? p0 >> (12 * lane) : p1 >> (12 * (lane - 5));
       ncnt = lane < kClasses ? (uint32_t)(pk & 0xFFF) : 0u;
     }
-    j = gget<COH>(&cin->j); acc = gget<COH>(&cin->acc); anchor = gget<COH>(&cin->anchor); dtot = 0;
+    j = rdl64(cv, 0); anchor = (int64_t)rdl64(cv, 1); acc = rdl64(cv, 2); dtot = 0;
     if (L.wipe && st.t_c > 0) {
       // wipe the slate (Sec. 5): the pending pair is dropped, the next one
       // starts its hazard at the window start
@@ -218,51 +326,27 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
   }
   const int nev0 = nev;
 
-  // ---- neighbour histories of the previous iteration (break points), each
-  // in the slot its owner last wrote; the first iteration assumes none
-  // (canonical assumption).  Merged into one stream in LDS.  The previous
-  // iteration's own lists come to LDS in the same pass: the end-of-run
-  // comparison then reads no global memory (a load there would wait for
-  // every store the run issued).
+  // ---- the list entries to LDS: the facing lists merged into one stream
+  // (break points), this subdomain's previous lists beside them (the
+  // end-of-run comparison then reads no global memory: a load there would
+  // wait for every store the run issued)
   uint64_t* raw = reinterpret_cast<uint64_t*>(lds);
   uint64_t* mrg = raw + 4 * hcap;
   uint64_t* lprev = raw + 8 * hcap;
   uint64_t* lcur = raw;                  // own lists of this run, once merged
-  int ni[4];
-  const uint64_t* li[4];
-  {
-    const int ev[4] = {dn, ds, dw, de};
-    const int ed[4] = {kS, kN, kE, kW};      // the neighbour's edge facing us
-    const bool none[4] = {first || wrapy, first || wrapy, first || wrapx, first || wrapx};
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      int sl = none[q] ? 0 : gget<COH>(&slot_prev[ev[q]]);
-      li[q] = hist_at(L, sl) + ((size_t)ev[q] * kEdges + ed[q]) * hcap;
-      ni[q] = none[q] ? 0 : clampn(gget<COH>(&hcnt_at(L, sl)[ev[q] * kEdges + ed[q]]));
-    }
-  }
-  const uint64_t* pb = hist_at(L, sprev) + (size_t)d * kEdges * hcap;
-  int np[4];
-#pragma unroll
-  for (int e = 0; e < 4; ++e) np[e] = first ? 0 : clampn(gget<COH>(&hcnt_at(L, sprev)[d * kEdges + e]));
-  const int o1 = ni[0], o2 = o1 + ni[1], o3 = o2 + ni[2], tot = o3 + ni[3];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int oq = q == 0 ? 0 : q == 1 ? o1 : q == 2 ? o2 : o3;
-    for (int i = lane; i < ni[q]; i += 64) {
-      uint64_t x = gget<COH>(&li[q][i]);
-      raw[oq + i] = ((x >> kPosBits) << kKeyShift) | ((uint64_t)q << 16) | (x & 0xFFFF);
-    }
-  }
-#pragma unroll
-  for (int e = 0; e < 4; ++e)
-    for (int i = lane; i < np[e]; i += 64) lprev[e * hcap + i] = gget<COH>(&pb[e * hcap + i]);
+  auto nb_key = [&](uint64_t x, int q) {
+    return ((x >> kPosBits) << kKeyShift) | ((uint64_t)q << 16) | (x & 0xFFFF);
+  };
+  if (lane < tot) { int q, k; nb_src(lane, q, k); raw[lane] = nb_key(xn, q); }
+  if (lane < totp) lprev[own_at(lane)] = xo;
+  for (int i = 64 + lane; i < tot; i += 64) { int q, k; const uint64_t x = gget<COH>(nb_src(i, q, k)); raw[i] = nb_key(x, q); }
+  for (int i = 64 + lane; i < totp; i += 64) lprev[own_at(i)] = gget<COH>(&pb[own_at(i)]);
   // committed digest and flip count of this subdomain, needed at the end;
   // the largest boundary-event count of its earlier runs in this window
-  const uint64_t dig_in = rdl64(gget<COH>(&cin->digest), 0);
-  const int64_t flips_in = (int64_t)rdl64((uint64_t)gget<COH>(&cin->flips), 0);
-  const int64_t nbmax_in = first ? 0 : (int64_t)rdl64((uint64_t)gget<COH>(&carry_at(L, st.wp ^ 1)[d].nbmax), 0);
-  const unsigned long long ev_in = rdl64(gget<COH>(&L.stat[d].events), 0), runs_in = rdl64(gget<COH>(&L.stat[d].runs), 0);
+  const uint64_t dig_in = rdl64(cv, 3);
+  const int64_t flips_in = (int64_t)rdl64(cv, 4);
+  const int64_t nbmax_in = first ? 0 : (int64_t)rdl64(cv, 5);
+  const unsigned long long ev_in = rdl64(cv, 6), runs_in = rdl64(cv, 7);
   __syncthreads();
   if (tot > 0) {
     for (int i = lane; i < tot; i += 64) {
@@ -303,13 +387,6 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
   int64_t next = next_tick(anchor, E, acc, lam);
 
   // window event log (tick << 16 | local site), buffered 64 at a time
-  uint64_t* wl = L.wlog + (size_t)d * L.wcap;
-  const int wcap = L.wcap;
-  uint64_t lbuf = 0;
-  {
-    int b = nev & ~63;
-    if (b + lane < nev && b + lane < wcap) lbuf = gget<COH>(&wl[b + lane]);
-  }
   auto log_flush = [&](int k) {          // k buffered entries in lanes 0..k-1
     int at = nev - k + lane;
     uint64_t dsum = 0;
