@@ -312,7 +312,9 @@ int sr_server_create(size_t hbm_budget, int32_t windows_per_round, void* hip_str
  * SR_ENOMEM if the request alone exceeds the budget. */
 int sr_server_submit(sr_server* v, const sr_params* p, uint64_t* req_id);
 /* One scheduling step (see above); waits at most about a millisecond for a
- * running launch.  *n_open (may be NULL) = requests not yet retired. */
+ * running launch.  *n_open (may be NULL) = requests not yet retired.  When a
+ * launch fails, its requests retire with the error code, which is returned,
+ * and the reason is sr_last_error(NULL) of the calling thread. */
 int sr_server_pump(sr_server* v, int32_t* n_open);
 /* Retired requests since the last poll, oldest first; up to cap into the
  * caller's array, *n = how many. */

@@ -1341,6 +1341,11 @@ extern "C" int sr_server_submit(sr_server* v, const sr_params* pin, uint64_t* re
 static int server_collect(sr_server* v) {
   BatchStage hs{v->st_lat.data(), v->st_run.data(), v->st_idx.data(), (int)v->st_idx.size()};
   int rc = batch_end(v->bl, hs);
+  // the reason of a failed launch outlives the simulations it finishes: it
+  // becomes the calling thread's last error
+  if (rc != SR_OK && rc != SR_ENOCONV)
+    for (auto& a : v->active)
+      if (!a.s->err.empty()) { g_create_err = "server launch: " + a.s->err; break; }
   v->running = false;
   v->busy_s += server_now(v) - v->t_launch;
   std::vector<sr_server::Active> keep;
@@ -1418,6 +1423,8 @@ extern "C" int sr_server_pump(sr_server* v, int32_t* n_open) {
       v->rounds++;
       v->running = v->bl.m > 0;
     } else {
+      for (auto& a : v->active)
+        if (!a.s->err.empty()) { g_create_err = "server launch: " + a.s->err; break; }
       for (auto& a : v->active) server_finish(v, a, rc);
       v->active.clear();
     }

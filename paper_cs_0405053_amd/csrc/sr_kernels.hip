@@ -98,6 +98,7 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
   // loop and kept in spilled registers
   int lane = lane_id();
   __asm__ volatile("" : "+v"(lane));
+  lane &= 63;                            // (its range, for the compiler)
   const int bx = BX ? BX : L.bx, by = BY ? BY : L.by;
   const int sh = BX ? lane_shift(BX * BY) : L.sshift, S = 1 << sh;
   const int nbx = L.nbx, nby = L.nby;
