@@ -854,12 +854,20 @@ __device__ uint32_t enqueue_iteration(const BatchArgs& B, int lat, LatRun* run, 
   const int off = lat % kShards;
   const int ls = (lane - off + kShards) % kShards;         // first task index of shard `lane`
   const uint32_t ns = lane < kShards ? (count > (uint32_t)ls ? (count - 1 - ls) / kShards + 1 : 0u) : 0u;
-  if (lane < kShards) gput<true>(&B.rem[(size_t)lat * kShards + lane].n, (int32_t)ns);
+  // the counts are set with returning memory-side atomics, not stores: the
+  // tasks count them down with memory-side atomics, and a store still on its
+  // way there could land after a fast task's decrement and undo it (the
+  // shard would then never reach zero and the lattice would stall)
+  // (the returned old values are kept live, so that the atomics return and
+  // the wait below waits until they were performed)
+  int32_t old_n = 0, old_s = 0;
+  if (lane < kShards) old_n = atomicExch(&B.rem[(size_t)lat * kShards + lane].n, (int32_t)ns);
   if (lane == 0) {
-    gput<true>(&run->shards_left, (int32_t)(count < (uint32_t)kShards ? count : (uint32_t)kShards));
+    old_s = atomicExch(&run->shards_left, (int32_t)(count < (uint32_t)kShards ? count : (uint32_t)kShards));
     gput<true>(&run->tasks, gget<true>(&run->tasks) + count);
   }
   publish_wait();
+  __asm__ volatile("" ::"v"(old_n), "v"(old_s));
   unsigned long long sbase = 0;
   if (lane < kShards && ns) sbase = atomicAdd(&B.ctr->sh[lane].tail, (unsigned long long)ns);
   unsigned long long bases[kShards];           // wave-uniform, read before the divergent walk
