@@ -97,6 +97,35 @@ static void server() {
   }
 }
 
+// A launch that gives up: the pump returns SR_EDEVICE, the reason is the
+// calling thread's last error, and the launch's requests retire with the
+// error while the server stays usable.
+static void server_give_up() {
+  sr_server* v = nullptr;
+  CHECK(sr_server_create((size_t)64 << 20, 3, nullptr, &v) == SR_OK);
+  for (int i = 0; i < 3; ++i) {
+    sr_params p = params(64, 0.0, 2.0, 7100 + i);
+    uint64_t id = 0;
+    CHECK(sr_server_submit(v, &p, &id) == SR_OK);
+  }
+  int32_t open = 0;
+  CHECK(sr_server_pump(v, &open) == SR_OK);        // admits and launches
+  int rc = SR_OK;
+  for (int r = 0; r < 100 && rc == SR_OK; ++r) rc = sr_server_pump(v, &open);
+  CHECK(rc == SR_EDEVICE);
+  const char* why = sr_last_error(nullptr);
+  std::printf("reason: %s\n", why);
+  CHECK(std::strstr(why, "server launch") && std::strstr(why, "gave up waiting"));
+  CHECK(open == 0);
+  sr_result res[4];
+  int32_t n = 0;
+  CHECK(sr_server_poll(v, res, 4, &n) == SR_OK && n == 3);
+  for (int i = 0; i < n; ++i) CHECK(res[i].status == SR_EDEVICE);
+  sr_server_info info;
+  CHECK(sr_server_stats(v, &info) == SR_OK && info.failed == 3 && info.bytes_in_use == 0);
+  sr_server_destroy(v);
+}
+
 // Budgeted batch steps, resumption, and the overflow fallback to the plain
 // path (buffers grown, the window re-run from its committed state).
 static void batch() {
@@ -304,6 +333,7 @@ int main(int argc, char** argv) {
   const char* w = argv[1];
   if (!std::strcmp(w, "tuned")) tuned();
   else if (!std::strcmp(w, "server")) server();
+  else if (!std::strcmp(w, "server_give_up")) server_give_up();
   else if (!std::strcmp(w, "batch")) batch();
   else if (!std::strcmp(w, "errors")) errors();
   else if (!std::strcmp(w, "threads")) threads();

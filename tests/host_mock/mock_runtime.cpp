@@ -7,7 +7,9 @@
 //                  the same step-size rule and window budget as the device
 //                  decider; SR_MOCK_OVERFLOW=1 makes lattice 0 report an
 //                  overflow of both buffers (2: of its window log only) so
-//                  that the plain fallback runs.
+//                  that the plain fallback runs; SR_MOCK_GIVE_UP=1 makes
+//                  lattice 0 stay running and the launch give up, as the
+//                  device kernel does when it waits far too long for work.
 #include "hip/hip_runtime.h"
 
 #include <cstdio>
@@ -241,6 +243,11 @@ hipError_t launch_batch(const BatchArgs& B, int, int, size_t, hipStream_t) {
   for (uint32_t k = 0; k < B.nlat; ++k) {
     LatRun& r = B.run[k];
     const int ovf = env_int("SR_MOCK_OVERFLOW", 0);
+    if (k == 0 && env_int("SR_MOCK_GIVE_UP", 0)) {
+      r.status = kRunning;
+      B.ctr->abort = 1;
+      continue;
+    }
     if (k == 0 && ovf) {
       // 1: both buffers overflowed; 2: only the window log did
       r.status = kOverflow;

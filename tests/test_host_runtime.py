@@ -71,6 +71,11 @@ def test_server_with_overflow_fallback(drive):
     run(drive, "server", SR_MOCK_G=3, SR_MOCK_OVERFLOW=1)
 
 
+def test_server_launch_that_gives_up_reports_why(drive):
+    out = run(drive, "server_give_up", SR_MOCK_GIVE_UP=1)
+    assert "gave up waiting" in out
+
+
 @pytest.mark.parametrize("overflow", [0, 1])
 def test_batch_budget_resume_reset(drive, overflow):
     run(drive, "batch", SR_MOCK_G=4, SR_MOCK_OVERFLOW=overflow)
