@@ -131,8 +131,8 @@ __device__ __forceinline__ void relax_subdomain(const LT& L, const Step& st, int
   // lengths, which pick the checkpoint to resume from (the latest one whose
   // state only depends on input entries that did not change); (3) that
   // checkpoint or the committed block, and the list entries.
-  const int ev[4] = {dn, ds, dw, de};
-  const int ed[4] = {kS, kN, kE, kW};      // the neighbour's edge facing us
+  // facing list q (0..3) is the list of neighbour dn, ds, dw, de on its
+  // edge kS, kN, kE, kW
   const bool none[4] = {first || wrapy, first || wrapy, first || wrapx, first || wrapx};
   const Ckpt* cks = L.ck + (size_t)d * L.nck;
   uint32_t g8 = 0;                         // lane 0: own slot; 1..4: facing slots; 5..8: their change masks
