@@ -550,7 +550,7 @@ def serve_run(sr, W, stream, n, rate, budget_gib=96, wpr=0):
             "latency_p50_s": round(float(np.percentile(lat, 50)), 3),
             "latency_p99_s": round(float(np.percentile(lat, 99)), 3),
             "service_p50_s": round(float(np.percentile(svc, 50)), 3),
-            "rounds": st["rounds"], "peak_active": st["peak_active"],
+            "rounds": st["rounds"], "peak_active": st["peak_active"], "restarts": st["restarts"],
             "peak_gib": round(st["peak_bytes"] / 2**30, 2), "wall_s": round(wall, 2),
             "gpu_busy_frac": round(st["busy_s"] / max(wall, 1e-9), 3)}, got, reqs
 

@@ -230,7 +230,10 @@ const char* sr_last_error(const sr_sim* s);
  * the last task of a lattice's iteration decides convergence and enqueues the
  * next iteration or the next window.  Results are bit-identical to
  * sr_run_window on each simulation alone.  All simulations must use
- * SR_LOG_DIGEST and the same stream. */
+ * SR_LOG_DIGEST and the same stream.  A launch whose waves find no work for
+ * far longer than any task takes gives up; the lattices it had not finished
+ * continue from their last committed window in another launch (the same
+ * results), and fail with SR_EDEVICE after 3 such launches in a row. */
 int sr_batch_run(sr_sim* const* sims, int32_t n, void* hip_stream);
 
 /* Batched form with a budget: every listed simulation commits at most
@@ -299,7 +302,9 @@ typedef struct {
 typedef struct {
   int64_t submitted, completed, failed, queued, rounds;
   int64_t bytes_in_use, peak_bytes;
-  int32_t peak_active, pad;
+  int32_t peak_active;
+  int32_t restarts;          /* lattices continued from their last committed
+                              * window after a launch gave up waiting for work */
   double busy_s, uptime_s;   /* time inside batch steps / since creation */
 } sr_server_info;
 

@@ -77,7 +77,7 @@ class Result(C.Structure):
 class ServerInfo(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
                 ("queued", C.c_int64), ("rounds", C.c_int64), ("bytes_in_use", C.c_int64),
-                ("peak_bytes", C.c_int64), ("peak_active", C.c_int32), ("pad", C.c_int32),
+                ("peak_bytes", C.c_int64), ("peak_active", C.c_int32), ("restarts", C.c_int32),
                 ("busy_s", C.c_double), ("uptime_s", C.c_double)]
 
 
@@ -392,7 +392,7 @@ class Server:
     def stats(self) -> Dict:
         o = ServerInfo()
         lib().sr_server_stats(self._h, C.byref(o))
-        return {k: getattr(o, k) for k, _ in ServerInfo._fields_ if k != "pad"}
+        return {k: getattr(o, k) for k, _ in ServerInfo._fields_}
 
     def close(self):
         if self._h is not None:

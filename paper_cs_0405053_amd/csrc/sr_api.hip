@@ -64,6 +64,13 @@ struct sr_sim {
   double relax_ms = 0.0;
   int64_t batch_tasks = 0;
   int failed = SR_OK;                   // last batched run ended in this error
+  // A persistent launch that gave up waiting for work before this lattice
+  // finished its window: it continues from its last committed window in a
+  // later launch (gave_up), unless that happened kMaxGiveUps times in a row.
+  bool gave_up = false;
+  int give_ups_in_row = 0;
+  int64_t restarts = 0;
+  int64_t call_windows0 = 0;            // windows before the current batch call
   uint8_t* need = nullptr;              // batched form's "runs now" bytes
   double last_batch_ms = 0.0;
   // captured windows: graph of k iterations, keyed by k (rebuilt when the
@@ -957,7 +964,11 @@ struct BatchLaunch {
   LatRun* drun = nullptr;
   BatchCounters* dctr = nullptr;
   bool fixed_mem = false;
+  int restarted = 0;               // lattices the launch gave up on (set by batch_end)
 };
+
+// Launches in a row that may give up on one lattice before it fails.
+constexpr int kMaxGiveUps = 3;
 
 // Enqueue one persistent launch over the listed simulations (sr_batch_step)
 // on `stream` and return without waiting: run records and counters prepared,
@@ -1077,6 +1088,7 @@ static int batch_begin(sr_sim* const* sims, int32_t n, int32_t max_windows, hipS
   bl.m = m;
   bl.drun = drun;
   bl.dctr = dctr;
+  bl.restarted = 0;
   return SR_OK;
 }
 
@@ -1137,11 +1149,21 @@ static int batch_end(BatchLaunch& bl, BatchStage& hs) {
     } else if (r.status == kNoConv) {
       one = SR_ENOCONV;
       s->err = "window did not converge within max_iters (batched run)";
+    } else if (r.status == kRunning && ctr.abort && ++s->give_ups_in_row <= kMaxGiveUps) {
+      // the launch gave up waiting for work before this lattice finished its
+      // window; the window's work is discarded and its committed state (the
+      // last converged window, whose time and parity the record holds) is
+      // intact, so it continues from there in a later launch, with the same
+      // results (the trajectory does not depend on how windows are run)
+      s->gave_up = true;
+      s->restarts++;
+      bl.restarted++;
     } else if (r.status != kDone && r.status != kPaused) {
       one = SR_EDEVICE;
       s->err = "batched run ended early (status " + std::to_string(r.status) +
                (ctr.abort ? ", the persistent kernel gave up waiting for work)" : ")");
     }
+    if (r.status == kDone || r.status == kPaused) s->give_ups_in_row = 0;
     s->failed = one;
     if (one != SR_OK && rc == SR_OK) { rc = one; first_bad = k; }
   }
@@ -1158,12 +1180,36 @@ static int batch_end(BatchLaunch& bl, BatchStage& hs) {
 
 // One synchronous persistent launch (sr_batch_step and its no-allocation
 // variant).
+// Lattices that a launch gave up on are launched again (listed in `retry`,
+// room for every lattice one launch takes), within what is left of their
+// window budget.
 static int batch_core(sr_sim* const* sims, int32_t n, int32_t max_windows, hipStream_t stream,
-                      BatchStage& hs, void* dev, size_t dev_cap) {
-  BatchLaunch bl;
-  int rc = batch_begin(sims, n, max_windows, stream, hs, dev, dev_cap, nullptr, nullptr, bl);
-  if (rc != SR_OK) return rc;
-  return batch_end(bl, hs);
+                      BatchStage& hs, void* dev, size_t dev_cap, sr_sim** retry) {
+  for (int32_t i = 0; i < n; ++i)
+    if (sims[i]) { sims[i]->call_windows0 = sims[i]->windows; sims[i]->gave_up = false; }
+  for (;;) {
+    BatchLaunch bl;
+    int rc = batch_begin(sims, n, max_windows, stream, hs, dev, dev_cap, nullptr, nullptr, bl);
+    if (rc != SR_OK) return rc;
+    rc = batch_end(bl, hs);
+    if (rc != SR_OK || bl.restarted == 0) return rc;
+    int32_t k = 0, left = max_windows;
+    for (int32_t i = 0; i < n; ++i) {
+      sr_sim* s = sims[i];
+      if (!s || !s->gave_up) continue;
+      s->gave_up = false;
+      if (max_windows > 0) {
+        const int64_t rest = max_windows - (s->windows - s->call_windows0);
+        if (rest <= 0) continue;
+        left = (int32_t)std::min<int64_t>(left, rest);
+      }
+      retry[k++] = s;
+    }
+    if (k == 0) return SR_OK;
+    sims = retry;
+    n = k;
+    max_windows = left;
+  }
 }
 
 extern "C" int sr_batch_step(sr_sim* const* sims, int32_t n, int32_t max_windows, void* stream_) {
@@ -1171,8 +1217,9 @@ extern "C" int sr_batch_step(sr_sim* const* sims, int32_t n, int32_t max_windows
   std::vector<Lattice> lat((size_t)n);
   std::vector<LatRun> run((size_t)n);
   std::vector<int> idx((size_t)n);
+  std::vector<sr_sim*> retry((size_t)n);
   BatchStage hs{lat.data(), run.data(), idx.data(), n};
-  return batch_core(sims, n, max_windows, (hipStream_t)stream_, hs, nullptr, 0);
+  return batch_core(sims, n, max_windows, (hipStream_t)stream_, hs, nullptr, 0, retry.data());
 }
 
 // ------------------------------------------------------------ no-allocation batch step
@@ -1190,6 +1237,7 @@ static void* g_scratch_ptr[kMaxDevices];        // device address of `scratch`, 
 static Lattice g_static_lat[kStaticMaxLattices]; // host staging (no allocation per call)
 static LatRun g_static_run[kStaticMaxLattices];
 static int g_static_idx[kStaticMaxLattices];
+static sr_sim* g_static_retry[kStaticMaxLattices];
 
 extern "C" int sr_batch_step_static(sr_sim* const* sims, int32_t n, int32_t max_windows, void* stream_) {
   if (!sims || n <= 0) SR_FAIL((sr_sim*)nullptr, SR_EINVAL, "sr_batch_step_static needs simulations");
@@ -1206,7 +1254,10 @@ extern "C" int sr_batch_step_static(sr_sim* const* sims, int32_t n, int32_t max_
     g_scratch_ptr[dev] = ptr;
   }
   BatchStage hs{g_static_lat, g_static_run, g_static_idx, kStaticMaxLattices};
-  return batch_core(sims, n, max_windows, (hipStream_t)stream_, hs, g_scratch_ptr[dev], kStaticScratchBytes);
+  // (lattices launched again go to g_static_retry: only launched lattices
+  // are, at most kStaticMaxLattices)
+  return batch_core(sims, n, max_windows, (hipStream_t)stream_, hs, g_scratch_ptr[dev], kStaticScratchBytes,
+                    g_static_retry);
 }
 
 // ------------------------------------------------------------ serving
@@ -1250,6 +1301,7 @@ struct sr_server {
   std::chrono::steady_clock::time_point t0;
   int64_t rounds = 0, completed = 0, failed = 0, submitted = 0;
   int32_t peak_active = 0;
+  int32_t restarts = 0;            // lattices launched again after a launch gave up on them
   double busy_s = 0.0;
   // the launch in flight
   bool running = false;
@@ -1348,6 +1400,7 @@ static int server_collect(sr_server* v) {
       if (!a.s->err.empty()) { g_create_err = "server launch: " + a.s->err; break; }
   v->running = false;
   v->busy_s += server_now(v) - v->t_launch;
+  v->restarts += v->bl.restarted;
   std::vector<sr_server::Active> keep;
   for (auto& a : v->active) {
     if (a.s->failed != SR_OK) server_finish(v, a, a.s->failed);
@@ -1455,6 +1508,7 @@ extern "C" int sr_server_stats(sr_server* v, sr_server_info* o) {
   o->bytes_in_use = (int64_t)v->used;
   o->peak_bytes = (int64_t)v->peak_used;
   o->peak_active = v->peak_active;
+  o->restarts = v->restarts;
   o->busy_s = v->busy_s;
   o->uptime_s = server_now(v);
   return SR_OK;

@@ -7,11 +7,13 @@
 //                  the same step-size rule and window budget as the device
 //                  decider; SR_MOCK_OVERFLOW=1 makes lattice 0 report an
 //                  overflow of both buffers (2: of its window log only) so
-//                  that the plain fallback runs; SR_MOCK_GIVE_UP=1 makes
-//                  lattice 0 stay running and the launch give up, as the
-//                  device kernel does when it waits far too long for work.
+//                  that the plain fallback runs; SR_MOCK_GIVE_UP=n makes the
+//                  first n launches leave lattice 0 running and give up, as
+//                  the device kernel does when it waits far too long for
+//                  work.
 #include "hip/hip_runtime.h"
 
+#include <atomic>
 #include <cstdio>
 #include <mutex>
 #include <set>
@@ -238,12 +240,14 @@ hipError_t launch_observables3d(const int8_t* s, int Lx, int Ly, int Lz, unsigne
   out[1] = 0;
   return hipSuccess;
 }
+static std::atomic<int> g_batch_launches{0};
 hipError_t launch_batch(const BatchArgs& B, int, int, size_t, hipStream_t) {
   const int G = env_int("SR_MOCK_G", 1);
+  const bool give_up = g_batch_launches++ < env_int("SR_MOCK_GIVE_UP", 0);
   for (uint32_t k = 0; k < B.nlat; ++k) {
     LatRun& r = B.run[k];
     const int ovf = env_int("SR_MOCK_OVERFLOW", 0);
-    if (k == 0 && env_int("SR_MOCK_GIVE_UP", 0)) {
+    if (k == 0 && give_up) {
       r.status = kRunning;
       B.ctr->abort = 1;
       continue;

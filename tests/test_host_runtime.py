@@ -71,9 +71,15 @@ def test_server_with_overflow_fallback(drive):
     run(drive, "server", SR_MOCK_G=3, SR_MOCK_OVERFLOW=1)
 
 
-def test_server_launch_that_gives_up_reports_why(drive):
-    out = run(drive, "server_give_up", SR_MOCK_GIVE_UP=1)
-    assert "gave up waiting" in out
+@pytest.mark.parametrize("give_ups", [1, 3, 100])
+def test_server_continues_lattices_a_launch_gave_up_on(drive, give_ups):
+    out = run(drive, "server_give_up", SR_MOCK_GIVE_UP=give_ups)
+    assert ("gave up waiting" in out) == (give_ups > 3)
+
+
+@pytest.mark.parametrize("give_ups", [2, 100])
+def test_batch_run_continues_lattices_a_launch_gave_up_on(drive, give_ups):
+    run(drive, "batch_give_up", SR_MOCK_GIVE_UP=give_ups)
 
 
 @pytest.mark.parametrize("overflow", [0, 1])
