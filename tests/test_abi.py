@@ -116,3 +116,36 @@ def test_tuner3_cubic_block():
     for L, want in ((8, 8), (16, 8), (12, 4), (20, 4), (6, 2), (64, 8)):
         bx, by, w = sr.tune(dict(Lx=L, Ly=L, Lz=L, T=4.0, horizon=1.0))
         assert (bx, by) == (want, want) and 0.125 <= w <= 2.0
+
+
+def test_binding_structures_match_the_header(tmp_path):
+    """Every structure the binding mirrors has the header's size and field
+    offsets (compiled from include/sr.h with the host C compiler)."""
+    import ctypes
+    import shutil
+    import paper_cs_0405053_amd as sr
+    cc = shutil.which("gcc")
+    if cc is None:
+        pytest.skip("gcc not available")
+    mirrors = {"sr_params": sr.Params, "sr_obs": sr.Obs, "sr_result": sr.Result,
+               "sr_server_info": sr.ServerInfo}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "sr.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    r = subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, timeout=60).stdout.splitlines():
+        name, field, value = line.split()
+        got[(name, field)] = int(value)
+    for cname, py in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
