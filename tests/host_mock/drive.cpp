@@ -162,6 +162,30 @@ static void batch_give_up() {
   for (sr_sim* s : sims) sr_destroy(s);
 }
 
+// Batched runs from four threads at once, each on its own simulations and
+// stream, with some launches giving up (SR_MOCK_GIVE_UP): every simulation
+// reaches its horizon.
+static void batch_threads() {
+  std::vector<std::thread> th;
+  for (int t = 0; t < 4; ++t) {
+    th.emplace_back([t]() {
+      std::vector<sr_sim*> sims;
+      for (int i = 0; i < 2; ++i) {
+        sr_params p = params(32 + 16 * i, 0.5, 2.0 + t, 500 + 10 * t + i);
+        sr_sim* s = nullptr;
+        CHECK(sr_create(&p, nullptr, &s) == SR_OK);
+        sims.push_back(s);
+      }
+      CHECK(sr_batch_step(sims.data(), 2, 2, nullptr) == SR_OK);
+      CHECK(sr_batch_run(sims.data(), 2, nullptr) == SR_OK);
+      sr_obs o;
+      for (sr_sim* s : sims) CHECK(sr_observables(s, &o) == SR_OK && o.tick == o.horizon_ticks);
+      for (sr_sim* s : sims) sr_destroy(s);
+    });
+  }
+  for (auto& x : th) x.join();
+}
+
 // Budgeted batch steps, resumption, and the overflow fallback to the plain
 // path (buffers grown, the window re-run from its committed state).
 static void batch() {
@@ -371,6 +395,7 @@ int main(int argc, char** argv) {
   else if (!std::strcmp(w, "server")) server();
   else if (!std::strcmp(w, "server_give_up")) server_give_up();
   else if (!std::strcmp(w, "batch_give_up")) batch_give_up();
+  else if (!std::strcmp(w, "batch_threads")) batch_threads();
   else if (!std::strcmp(w, "batch")) batch();
   else if (!std::strcmp(w, "errors")) errors();
   else if (!std::strcmp(w, "threads")) threads();

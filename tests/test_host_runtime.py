@@ -106,6 +106,16 @@ def test_threads_drive_separate_simulations(drive):
     run(drive, "threads", SR_MOCK_G=3)
 
 
+def test_batched_runs_from_threads_with_give_ups(drive):
+    run(drive, "batch_threads", SR_MOCK_G=2, SR_MOCK_GIVE_UP=3)
+
+
+def test_batched_runs_from_threads_without_data_races(drive_tsan):
+    r = subprocess.run([drive_tsan, "batch_threads"], capture_output=True, text=True, timeout=300,
+                       env=dict(os.environ, SR_MOCK_G="2", SR_MOCK_GIVE_UP="3", TSAN_OPTIONS="halt_on_error=1"))
+    assert r.returncode == 0 and "ok batch_threads" in r.stdout, (r.stdout + r.stderr)[-4000:]
+
+
 def test_threads_without_data_races(drive_tsan):
     # ThreadSanitizer: the only state shared between handles is the
     # per-thread creation error
