@@ -1013,13 +1013,12 @@ constexpr uint32_t kProgressEvery = 4096;
 
 // Wave w serves shard w % kShards (the dispatcher places workgroup w on XCD
 // w % kShards, so each shard's counters are hit from one XCD).  Per task:
-// wait for the slot of the ticket held, acquire, relax, publish, count the
-// task down while taking the next ticket.
+// wait for the slot of the ticket held, relax, publish (wait for the run's
+// stores), count the task down while taking the next ticket.
 // A held ticket whose task is not produced yet blocks no one: tasks are
 // produced by deciders, and a wave finishes its current task before it waits.
-// Registers are capped so that six waves share a SIMD (80 VGPRs; the few
-// spills are reloaded once per task, never in the event loop): more waves
-// hide more of each task's latency chain.
+// Registers are capped so that six waves share a SIMD (80 VGPRs, no
+// spills): more waves hide more of each task's latency chain.
 // BX, BY, NW as for the plain kernels: <16, 16, true> (constant index
 // arithmetic, no wrap handling) for launches whose lattices all have 16x16
 // blocks and two or more subdomains per direction, <0, 0, false> otherwise;
@@ -1208,10 +1207,9 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t stream) {
   return hipGetLastError();
 }
 
-// Both instantiations run six waves per SIMD (80 VGPRs).  The 16x16 body
-// would take 118 without the cap; capped, its spills are reloaded once per
-// task, outside the event loop, and it is faster than at four waves without
-// spills (512-lattice batch 2.93 s against 3.45 s per launch).
+// Both instantiations run six waves per SIMD (80 VGPRs, no spills); more
+// or fewer waves per SIMD were slower (512-lattice batch 1.42 s at six
+// against 1.68 / 1.44 / 1.53 s at four / seven / eight).
 static const void* batch_kernel_for(int shape) {
   return shape == kBatch16NoWrap ? (const void*)batch_kernel<16, 16, true, 6> : (const void*)batch_kernel<0, 0, false, 6>;
 }
